@@ -1,0 +1,178 @@
+/*
+ * spg.h -- C ABI of the MI355X (gfx950) solver for the reweighted weighted-l1 plus
+ * total-variation reconstruction of a density map by the smoothing proximal
+ * gradient (SPG) method (Luo, "Improving the resolution of Cryo-EM single particle
+ * analysis", arXiv 1905.13408, section 2 eq 8-22 and section 2.5 eq 31).
+ *
+ * Problem solved (eq 31 with the reweighted penalties of eq 11 and the Nesterov
+ * smoothing of eq 14; paper letters in brackets):
+ *
+ *   min_x  1/2 sum_k w_k |(A x)_k - b_k|^2            data term, A = unitary 3D DFT
+ *        + lambda sum_i u_i |x_i|                      weighted l1        [alpha, w'_j]
+ *        + mu     sum_i v_i phi_eps(|(D x)_i|_2)       weighted smoothed TV [beta, w_j, mu]
+ *
+ * x is a real nz*ny*nx map in C order (x fastest).  D is the backward difference
+ * of eq 12 with periodic wrap; phi_eps is the per-voxel value of eq 14
+ * (t^2/(2 eps) below eps, t - eps/2 above).  One SPG iteration (eq 20-21 with
+ * Beck-Teboulle momentum) is
+ *
+ *   y   = x_k + m_k (x_k - x_{k-1})
+ *   z   = y - lr (Re A^H(w (A y - b)) + mu D^T(v * Dy / max(eps, |Dy|)))
+ *   x_{k+1} = sign(z) max(|z| - lr lambda u, 0)
+ *
+ * with lr = 1/L, L = max_k (w_k + w_{-k})/2 + mu max(v) ||D||^2 / eps.
+ * Reweighting (eq 11) sets u = 1/(|x| + eps1), v = 1/(|Dx| + eps2) from the
+ * current map and restarts the momentum.
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers on the current HIP device, owned by
+ *    the caller.  Calls are asynchronous on the problem's stream unless stated;
+ *    the caller keeps inputs alive until the stream has passed the call.
+ *  - The library allocates no device memory: all state lives in the caller's
+ *    workspace (size from spg_workspace_size).  It creates HIP events only
+ *    while profiling is enabled.
+ *  - Arguments are validated on the host before anything is enqueued; a call
+ *    that returns an error leaves the problem as it was.  A HIP error makes the
+ *    problem return SPG_E_DEVICE from then on.
+ *  - A problem belongs to one stream and is not thread-safe; distinct problems
+ *    are independent.
+ */
+#ifndef SPG_H
+#define SPG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SPG_OK = 0,
+  SPG_E_INVAL = -1,       /* bad argument (pointer, size, value)                    */
+  SPG_E_NOMEM = -2,       /* workspace smaller than spg_workspace_size              */
+  SPG_E_DEVICE = -3,      /* a HIP call failed; the problem is unusable             */
+  SPG_E_STATE = -4,       /* call out of order (e.g. run before set_data)           */
+  SPG_E_NONFINITE = -5,   /* non-finite value in w, b, u or v                       */
+  SPG_E_DIVERGED = -6,    /* non-finite objective found by spg_final_check          */
+  SPG_E_UNSUPPORTED = -7  /* valid request this build does not implement            */
+} spg_status;
+
+typedef struct spg_problem spg_problem;   /* opaque, owned by the library */
+
+/* Flag bits of spg_params.flags. */
+#define SPG_FLAG_COMPENSATED 1   /* iterate stored as fp32 hi + bf16 lo (about 32 significant
+                                    bits) with the prox and momentum in fp64; without it the
+                                    iterate is plain fp32 and all arithmetic is fp32        */
+
+typedef struct {
+  int32_t nx, ny, nz;   /* grid; each a power of two in [4, 512]                        */
+  double lambda;        /* l1 weight (paper alpha), >= 0                                */
+  double mu;            /* TV weight (paper beta), >= 0                                 */
+  double eps;           /* Nesterov smoothing parameter (paper mu in eq 14), > 0        */
+  double gamma;         /* implicit-descent weight of eq 22; must be 0 in this build    */
+  int32_t accel;        /* 1: FISTA momentum (default); 0: un-accelerated eq 20-21      */
+  int32_t flags;        /* SPG_FLAG_* bits                                              */
+} spg_params;
+
+typedef struct {
+  int64_t iters_done;   /* iterations since spg_create                                   */
+  int32_t round;        /* 1 + number of spg_reweight calls                              */
+  int32_t iter_in_round;/* iterations since the last momentum restart                    */
+  double lr;            /* current step 1/L                                              */
+  double L;             /* current Lipschitz bound                                       */
+} spg_stats;
+
+/* Bytes of device workspace a problem with these parameters needs (host only,
+ * no HIP call).  SPG_E_INVAL for invalid parameters. */
+spg_status spg_workspace_size(const spg_params* p, size_t* bytes);
+
+/* Create a problem whose state lives in d_workspace (>= spg_workspace_size bytes,
+ * 256-byte aligned, device memory that the caller frees after spg_destroy).
+ * hip_stream is a hipStream_t (NULL = the default stream).  Uploads FFT twiddle
+ * tables (computed in fp64 on the host) and synchronises the stream once. */
+spg_status spg_create(const spg_params* p, void* d_workspace, size_t bytes, void* hip_stream,
+                      spg_problem** out);
+
+/* Destroy the problem object (host memory only; the workspace stays the caller's). */
+spg_status spg_destroy(spg_problem* P);
+
+/* Set the Fourier-space weights w (N(n) of eq 28; nz*ny*nx float, >= 0, FFT order:
+ * index 0 is the zero frequency on every axis) and the data b (y(n)/sqrt(N(n)) of
+ * eq 31; nz*ny*nx complex, interleaved re/im float pairs, FFT order).  The pair is
+ * folded onto the half spectrum a real map needs (w~ = (w_k + w_{-k})/2 and
+ * c = (w_k b_k + w_{-k} conj b_{-k})/2).  Synchronises the stream to check the
+ * inputs: SPG_E_NONFINITE for NaN/Inf, SPG_E_INVAL for a negative weight or w == 0
+ * everywhere with mu == 0.  Resets the momentum. */
+spg_status spg_set_data(spg_problem* P, const float* d_w, const float* d_b);
+
+/* Set the reweighting weights u (l1) and v (TV) of eq 11, nz*ny*nx float each,
+ * finite and >= 0; NULL means uniform weight 1.  Copied into the workspace.
+ * Synchronises to check them and to read max(v).  Resets the momentum. */
+spg_status spg_set_penalty_weights(spg_problem* P, const float* d_u, const float* d_v);
+
+/* Change lambda and mu (both >= 0).  Recomputes L; resets the momentum. */
+spg_status spg_set_params(spg_problem* P, double lambda, double mu);
+
+/* Set the current map x_0 (nz*ny*nx float) or, with NULL, x_0 = 0.  Resets the momentum. */
+spg_status spg_set_map(spg_problem* P, const float* d_x0);
+
+/* Run K >= 0 SPG iterations (eq 20-21 with momentum) on the stream.  Does not
+ * synchronise.  opt_stats (may be NULL) receives the counters after the launches. */
+spg_status spg_run(spg_problem* P, int32_t K, spg_stats* opt_stats);
+
+/* Reweight (eq 11): u = 1/(|x| + eps1), v = 1/(|Dx|_2 + eps2) from the current map,
+ * then recompute L and restart the momentum.  eps1, eps2 > 0.  Synchronises to read
+ * max(v) (8 bytes). */
+spg_status spg_reweight(spg_problem* P, double eps1, double eps2);
+
+/* Copy the current map x_K (the last prox output, rounded to float) to d_x_out
+ * (nz*ny*nx float). */
+spg_status spg_get_map(spg_problem* P, float* d_x_out);
+
+/* Copy the current penalty weights to d_u_out / d_v_out (either may be NULL). */
+spg_status spg_get_penalty_weights(spg_problem* P, float* d_u_out, float* d_v_out);
+
+/* Evaluate, with fp64 accumulation, at the current map x: the smoothed objective
+ * F_eps(x) (eq 31 with eq 14), the unsmoothed objective F_0(x) (eq 31), and the
+ * relative fixed-point residual |x - T(x)| / |x| of one un-accelerated step T
+ * (eq 20-21), zero exactly at the minimiser.  Any output may be NULL.  Uses one
+ * extra forward/inverse FFT pair and synchronises.  SPG_E_DIVERGED if F_eps is
+ * not finite.  Leaves the iteration state unchanged. */
+spg_status spg_final_check(spg_problem* P, double* F_eps, double* F_0, double* kkt_rel);
+
+/* Checkpoint: bytes needed by spg_get_state, then copy the iteration state (current
+ * and previous map, momentum counters, L, round) into / out of a caller device buffer.
+ * Restoring into a problem with the same parameters, data and penalty weights gives
+ * bitwise the same future iterates as the uninterrupted run. */
+spg_status spg_state_size(const spg_problem* P, size_t* bytes);
+spg_status spg_get_state(spg_problem* P, void* d_buf, size_t bytes);
+spg_status spg_set_state(spg_problem* P, const void* d_buf, size_t bytes);
+
+/* Kernel classes for spg_profile_begin. */
+typedef enum {
+  SPG_KERNEL_FFT_Y_FWD = 0, /* y-axis forward column FFT                               */
+  SPG_KERNEL_FFT_Z_WEIGHT,  /* z-axis forward FFT, Fourier weight multiply, inverse FFT  */
+  SPG_KERNEL_DC_NYQUIST,    /* the packed kx = 0 / kx = nx/2 plane of the z pass         */
+  SPG_KERNEL_FFT_Y_INV,     /* y-axis inverse column FFT                               */
+  SPG_KERNEL_C2R_X,         /* x-axis inverse real FFT of the gradient spectrum         */
+  SPG_KERNEL_PROX_TV,       /* smoothed-TV stencil, gradient step, soft threshold, momentum */
+  SPG_KERNEL_R2C_X,         /* x-axis forward real FFT of the extrapolated map          */
+  SPG_KERNEL_COUNT
+} spg_kernel_class;
+
+/* Profiling: time every launch of one kernel class with HIP events recorded on the
+ * problem's stream around it, for at most `capacity` launches.  spg_profile_end
+ * synchronises and returns the summed device time (ms) and the launch count. */
+spg_status spg_profile_begin(spg_problem* P, int32_t kernel_class, int32_t capacity);
+spg_status spg_profile_end(spg_problem* P, double* total_ms, int32_t* launches);
+
+/* Static message for a status code; per-problem message of the last error. */
+const char* spg_status_string(spg_status s);
+const char* spg_last_error(const spg_problem* P);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPG_H */

@@ -1,0 +1,666 @@
+// Host runtime of the SPG solver: validation, workspace carving, launch sequence and the
+// extern "C" entry points declared in include/spg.h.  All device state lives in the
+// caller's workspace; this file allocates host memory only (and HIP events while
+// profiling is on).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/spg.h"
+#include "spg_internal.h"
+
+using namespace spg;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kStatBlocks = 1024;           // grid of the input-check / reweight kernels
+constexpr int kPartials = 65536;            // fp64 partials in the workspace
+constexpr int kPartA = 0;                   // z-pass objective partials (<= 8192 blocks)
+constexpr int kPartB = 8192;                // kx = 0 / nx/2 plane partials (<= 257 blocks)
+constexpr int kPartC = 16384;               // stencil check partials (5 x <= 8192)
+constexpr uint64_t kStateMagic = 0x5350475354415431ull;  // "SPGSTAT1"
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+struct Layout {
+  size_t xhi[3], xlo[3], u, v, S, rbuf, ws, wnyq, cs, cnyq, tw_m, tw_n, tw_y, tw_z, part, res, total;
+};
+
+Layout make_layout(const spg_params& p) {
+  Layout L{};
+  const size_t nvox = (size_t)p.nx * p.ny * p.nz;
+  const size_t P = (size_t)p.nx / 2;
+  const bool comp = (p.flags & SPG_FLAG_COMPENSATED) != 0;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  for (int s = 0; s < 3; ++s) L.xhi[s] = take(nvox * 4);
+  for (int s = 0; s < 3; ++s) L.xlo[s] = comp ? take(nvox * 2) : 0;
+  L.u = take(nvox * 4);
+  L.v = take(nvox * 4);
+  L.S = take((size_t)p.nz * p.ny * P * 8);
+  L.rbuf = take(nvox * 4);
+  L.ws = take((size_t)p.nz * p.ny * P * 4);
+  L.wnyq = take((size_t)p.nz * p.ny * 4);
+  L.cs = take((size_t)p.nz * p.ny * P * 8);
+  L.cnyq = take((size_t)p.nz * p.ny * 8);
+  L.tw_m = take(P * 8);
+  L.tw_n = take((size_t)p.nx * 8);
+  L.tw_y = take((size_t)p.ny * 8);
+  L.tw_z = take((size_t)p.nz * 8);
+  L.part = take((size_t)kPartials * 8);
+  L.res = take(64 * 8);
+  L.total = off;
+  return L;
+}
+
+const char* check_params(const spg_params* p, spg_status* st) {
+  *st = SPG_E_INVAL;
+  if (!p) return "params is NULL";
+  if (!pow2_in(p->nx, 4, 512) || !pow2_in(p->ny, 4, 512) || !pow2_in(p->nz, 4, 512))
+    return "nx, ny, nz must be powers of two in [4, 512]";
+  if (!std::isfinite(p->lambda) || p->lambda < 0) return "lambda must be finite and >= 0";
+  if (!std::isfinite(p->mu) || p->mu < 0) return "mu must be finite and >= 0";
+  if (!std::isfinite(p->eps) || p->eps <= 0) return "eps must be finite and > 0";
+  if (!std::isfinite(p->gamma) || p->gamma < 0) return "gamma must be finite and >= 0";
+  if (p->accel != 0 && p->accel != 1) return "accel must be 0 or 1";
+  if (p->flags & ~SPG_FLAG_COMPENSATED) return "unknown flag bits";
+  if (p->gamma != 0) {
+    *st = SPG_E_UNSUPPORTED;
+    return "gamma != 0 (implicit-descent term) is not implemented in this build";
+  }
+  *st = SPG_OK;
+  return nullptr;
+}
+
+double dnorm2_of(int nx, int ny, int nz) {
+  // largest eigenvalue of D^T D for periodic backward differences: 4 per even axis
+  double s = 0;
+  const int ns[3] = {nx, ny, nz};
+  for (int a = 0; a < 3; ++a) {
+    double m = 0;
+    for (int k = 0; k < ns[a]; ++k) {
+      const double v = 4.0 * std::pow(std::sin(M_PI * k / ns[a]), 2);
+      m = v > m ? v : m;
+    }
+    s += m;
+  }
+  return s;
+}
+
+}  // namespace
+
+struct spg_problem {
+  spg_params prm{};
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  Layout lay{};
+  Dims d{};
+  bool comp = false;
+  bool data_set = false;
+  bool primed = false;
+  bool sticky = false;
+  bool unif_u = true, unif_v = true;
+  double maxwt = 0, vmax = 1, C0 = 0, L = 0, lr = 0, dn2 = 12;
+  int cur = 0, old = 1;
+  int64_t iters_done = 0;
+  int32_t round = 1;
+  int32_t j = 1;         // index of the next iteration within the round (1-based)
+  double t = 1.0;        // FISTA t_j
+  double m_cur = 0.0;    // momentum m_j of y_j
+  char err[512] = {0};
+  // profiling
+  int prof_class = -1, prof_cap = 0, prof_n = 0;
+  std::vector<hipEvent_t> ev;
+
+  template <typename T>
+  T* at(size_t off) { return reinterpret_cast<T*>(ws + off); }
+  float* xhi(int s) { return at<float>(lay.xhi[s]); }
+  uint16_t* xlo(int s) { return comp ? at<uint16_t>(lay.xlo[s]) : nullptr; }
+  float2* S() { return at<float2>(lay.S); }
+  float* rbuf() { return at<float>(lay.rbuf); }
+  double* part() { return at<double>(lay.part); }
+  double* res() { return at<double>(lay.res); }
+  const float* uptr() { return unif_u ? nullptr : at<float>(lay.u); }
+  const float* vptr() { return unif_v ? nullptr : at<float>(lay.v); }
+};
+
+namespace {
+
+spg_status set_err(spg_problem* P, spg_status s, const char* fmt, const char* a = "") {
+  if (P) std::snprintf(P->err, sizeof(P->err), fmt, a);
+  return s;
+}
+
+spg_status fail_device(spg_problem* P, hipError_t e, const char* what) {
+  P->sticky = true;
+  std::snprintf(P->err, sizeof(P->err), "HIP error in %s: %s", what, hipGetErrorString(e));
+  return SPG_E_DEVICE;
+}
+
+#define SPG_CK(P, expr)                                         \
+  do {                                                          \
+    hipError_t e_ = (expr);                                     \
+    if (e_ != hipSuccess) return fail_device((P), e_, #expr);   \
+  } while (0)
+
+spg_status usable(spg_problem* P) {
+  if (!P) return SPG_E_INVAL;
+  if (P->sticky) return SPG_E_DEVICE;
+  return SPG_OK;
+}
+
+void recompute_L(spg_problem* P) {
+  P->L = P->maxwt + P->prm.mu * P->vmax * P->dn2 / P->prm.eps + 2.0 * P->prm.gamma;
+  P->lr = P->L > 0 ? 1.0 / P->L : 0.0;
+}
+
+void restart(spg_problem* P) {
+  P->j = 1;
+  P->t = 1.0;
+  P->m_cur = 0.0;
+  P->primed = false;
+}
+
+// Profiling hooks around one launch of kernel class cls.
+void prof_begin(spg_problem* P, int cls) {
+  if (P->prof_class == cls && P->prof_n < P->prof_cap) (void)hipEventRecord(P->ev[2 * P->prof_n], P->stream);
+}
+void prof_end(spg_problem* P, int cls) {
+  if (P->prof_class == cls && P->prof_n < P->prof_cap) {
+    (void)hipEventRecord(P->ev[2 * P->prof_n + 1], P->stream);
+    ++P->prof_n;
+  }
+}
+
+spg_status read_results(spg_problem* P, double* host, int n) {
+  SPG_CK(P, hipMemcpyAsync(host, P->res(), n * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  SPG_CK(P, hipStreamSynchronize(P->stream));
+  return SPG_OK;
+}
+
+// Forward FFT of the x-axis rows of rbuf (already holding y) followed by the y, z
+// passes with the weight step, the y inverse and the x inverse into rbuf.  obj: also
+// collect the data-term partials.
+spg_status gradient_pipeline(spg_problem* P, bool obj, int* nA, int* nB) {
+  const Dims& d = P->d;
+  hipStream_t st = P->stream;
+  const float2* twy = P->at<float2>(P->lay.tw_y);
+  const float2* twz = P->at<float2>(P->lay.tw_z);
+  const float* wsp = P->at<float>(P->lay.ws);
+  const float2* csp = P->at<float2>(P->lay.cs);
+  prof_begin(P, SPG_KERNEL_FFT_Y_FWD);
+  SPG_CK(P, launch_fft_cols(d, P->S(), 1, 0, twy, nullptr, nullptr, nullptr, st, nullptr));
+  prof_end(P, SPG_KERNEL_FFT_Y_FWD);
+  prof_begin(P, SPG_KERNEL_FFT_Z_WEIGHT);
+  SPG_CK(P, launch_fft_cols(d, P->S(), 2, obj ? 3 : 2, twz, wsp, csp, obj ? P->part() + kPartA : nullptr, st, nA));
+  prof_end(P, SPG_KERNEL_FFT_Z_WEIGHT);
+  prof_begin(P, SPG_KERNEL_DC_NYQUIST);
+  SPG_CK(P, launch_dc_nyquist(d, P->S(), twz, wsp, P->at<float>(P->lay.wnyq), csp, P->at<float2>(P->lay.cnyq),
+                              obj ? P->part() + kPartB : nullptr, st, nB));
+  prof_end(P, SPG_KERNEL_DC_NYQUIST);
+  prof_begin(P, SPG_KERNEL_FFT_Y_INV);
+  SPG_CK(P, launch_fft_cols(d, P->S(), 1, 1, twy, nullptr, nullptr, nullptr, st, nullptr));
+  prof_end(P, SPG_KERNEL_FFT_Y_INV);
+  prof_begin(P, SPG_KERNEL_C2R_X);
+  SPG_CK(P, launch_c2r_x(d, P->S(), P->rbuf(), P->at<float2>(P->lay.tw_m), P->at<float2>(P->lay.tw_n), st));
+  prof_end(P, SPG_KERNEL_C2R_X);
+  return SPG_OK;
+}
+
+spg_status r2c(spg_problem* P) {
+  prof_begin(P, SPG_KERNEL_R2C_X);
+  SPG_CK(P, launch_r2c_x(P->d, P->rbuf(), P->S(), P->at<float2>(P->lay.tw_m), P->at<float2>(P->lay.tw_n),
+                         P->stream));
+  prof_end(P, SPG_KERNEL_R2C_X);
+  return SPG_OK;
+}
+
+ProxArgs prox_args(spg_problem* P, int nxt, double m, double m_next) {
+  ProxArgs a{};
+  a.rbuf = P->rbuf();
+  a.xk_hi = P->xhi(P->cur);
+  a.xk_lo = P->xlo(P->cur);
+  a.xo_hi = P->xhi(P->old);
+  a.xo_lo = P->xlo(P->old);
+  a.xn_hi = P->xhi(nxt);
+  a.xn_lo = P->xlo(nxt);
+  a.u = P->uptr();
+  a.v = P->vptr();
+  a.partials = nullptr;
+  a.nx = P->d.nx;
+  a.ny = P->d.ny;
+  a.nz = P->d.nz;
+  a.read_old = m != 0.0 ? 1 : 0;
+  a.m = m;
+  a.m_next = m_next;
+  a.lr = P->lr;
+  a.lam = P->prm.lambda;
+  a.mu = P->prm.mu;
+  a.eps = (float)P->prm.eps;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* spg_status_string(spg_status s) {
+  switch (s) {
+    case SPG_OK: return "ok";
+    case SPG_E_INVAL: return "invalid argument";
+    case SPG_E_NOMEM: return "workspace too small";
+    case SPG_E_DEVICE: return "device (HIP) error";
+    case SPG_E_STATE: return "call out of order";
+    case SPG_E_NONFINITE: return "non-finite input";
+    case SPG_E_DIVERGED: return "objective is not finite";
+    case SPG_E_UNSUPPORTED: return "unsupported by this build";
+  }
+  return "unknown status";
+}
+
+const char* spg_last_error(const spg_problem* P) { return P ? P->err : "problem is NULL"; }
+
+spg_status spg_workspace_size(const spg_params* p, size_t* bytes) {
+  spg_status st;
+  if (check_params(p, &st)) return st;
+  if (!bytes) return SPG_E_INVAL;
+  *bytes = make_layout(*p).total;
+  return SPG_OK;
+}
+
+spg_status spg_create(const spg_params* p, void* d_workspace, size_t bytes, void* hip_stream, spg_problem** out) {
+  spg_status st;
+  if (!out) return SPG_E_INVAL;
+  *out = nullptr;
+  if (check_params(p, &st)) return st;
+  if (!d_workspace || (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0) return SPG_E_INVAL;
+  const Layout lay = make_layout(*p);
+  if (bytes < lay.total) return SPG_E_NOMEM;
+  spg_problem* P = new (std::nothrow) spg_problem();
+  if (!P) return SPG_E_NOMEM;
+  P->prm = *p;
+  P->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  P->ws = reinterpret_cast<char*>(d_workspace);
+  P->ws_bytes = bytes;
+  P->lay = lay;
+  P->d.nx = p->nx;
+  P->d.ny = p->ny;
+  P->d.nz = p->nz;
+  P->d.P = p->nx / 2;
+  P->d.nvox = (long long)p->nx * p->ny * p->nz;
+  P->comp = (p->flags & SPG_FLAG_COMPENSATED) != 0;
+  P->dn2 = dnorm2_of(p->nx, p->ny, p->nz);
+
+  // Twiddle tables exp(-2 pi i m / n), computed in fp64 and rounded once.
+  const int lens[4] = {p->nx / 2, p->nx, p->ny, p->nz};
+  const size_t offs[4] = {lay.tw_m, lay.tw_n, lay.tw_y, lay.tw_z};
+  std::vector<float2> tab;
+  for (int t = 0; t < 4; ++t) {
+    const int n = lens[t];
+    tab.resize(n);
+    for (int m = 0; m < n; ++m) {
+      const double ang = -2.0 * M_PI * (double)m / (double)n;
+      tab[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    hipError_t e = hipMemcpyAsync(P->ws + offs[t], tab.data(), n * sizeof(float2), hipMemcpyHostToDevice, P->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
+    if (e != hipSuccess) {
+      delete P;
+      return SPG_E_DEVICE;
+    }
+  }
+  if (launch_set_map(P->d, nullptr, P->xhi(P->cur), P->xlo(P->cur), P->stream) != hipSuccess) {
+    delete P;
+    return SPG_E_DEVICE;
+  }
+  restart(P);
+  *out = P;
+  return SPG_OK;
+}
+
+spg_status spg_destroy(spg_problem* P) {
+  if (!P) return SPG_E_INVAL;
+  for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
+  delete P;
+  return SPG_OK;
+}
+
+spg_status spg_set_data(spg_problem* P, const float* d_w, const float* d_b) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if (!d_w || !d_b) return set_err(P, SPG_E_INVAL, "w and b must be device pointers");
+  const Dims& d = P->d;
+  const float2* b = reinterpret_cast<const float2*>(d_b);
+  double* part = P->part();
+  // 1. check the inputs before touching any state
+  SPG_CK(P, launch_data_stats(d, d_w, b, part, kStatBlocks, P->stream));
+  const int ops3[3] = {RED_OP_SUM, RED_OP_MIN, RED_OP_SUM};
+  SPG_CK(P, launch_reduce(part, kStatBlocks, 3, ops3, P->res(), P->stream));
+  double r[3];
+  if ((s = read_results(P, r, 3))) return s;
+  if (r[0] > 0) return set_err(P, SPG_E_NONFINITE, "w or b holds NaN/Inf values");
+  if (r[1] < 0) return set_err(P, SPG_E_INVAL, "negative Fourier weight");
+  // 2. fold onto the packed half spectrum
+  SPG_CK(P, launch_fold(d, d_w, b, P->at<float>(P->lay.ws), P->at<float>(P->lay.wnyq), P->at<float2>(P->lay.cs),
+                        P->at<float2>(P->lay.cnyq), part, kStatBlocks, P->stream));
+  const int ops1[1] = {RED_OP_MAX};
+  SPG_CK(P, launch_reduce(part, kStatBlocks, 1, ops1, P->res(), P->stream));
+  double mx;
+  if ((s = read_results(P, &mx, 1))) return s;
+  P->maxwt = mx;
+  P->C0 = r[2];
+  P->data_set = true;
+  recompute_L(P);
+  restart(P);
+  if (P->L <= 0) return set_err(P, SPG_E_INVAL, "L = 0: all weights are zero and mu == 0");
+  return SPG_OK;
+}
+
+spg_status spg_set_penalty_weights(spg_problem* P, const float* d_u, const float* d_v) {
+  spg_status s = usable(P);
+  if (s) return s;
+  double vmax = 1.0;
+  const float* arr[2] = {d_u, d_v};
+  for (int k = 0; k < 2; ++k) {
+    if (!arr[k]) continue;
+    SPG_CK(P, launch_weight_stats(P->d, arr[k], P->part(), kStatBlocks, P->stream));
+    const int ops[3] = {RED_OP_SUM, RED_OP_MIN, RED_OP_MAX};
+    SPG_CK(P, launch_reduce(P->part(), kStatBlocks, 3, ops, P->res(), P->stream));
+    double r[3];
+    if ((s = read_results(P, r, 3))) return s;
+    if (r[0] > 0) return set_err(P, SPG_E_NONFINITE, "penalty weights hold NaN/Inf values");
+    if (r[1] < 0) return set_err(P, SPG_E_INVAL, "negative penalty weight");
+    if (k == 1) vmax = r[2];
+  }
+  const size_t bytes = (size_t)P->d.nvox * 4;
+  if (d_u) SPG_CK(P, hipMemcpyAsync(P->at<float>(P->lay.u), d_u, bytes, hipMemcpyDeviceToDevice, P->stream));
+  if (d_v) SPG_CK(P, hipMemcpyAsync(P->at<float>(P->lay.v), d_v, bytes, hipMemcpyDeviceToDevice, P->stream));
+  P->unif_u = d_u == nullptr;
+  P->unif_v = d_v == nullptr;
+  P->vmax = vmax;
+  recompute_L(P);
+  restart(P);
+  return SPG_OK;
+}
+
+spg_status spg_set_params(spg_problem* P, double lambda, double mu) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if (!std::isfinite(lambda) || lambda < 0 || !std::isfinite(mu) || mu < 0)
+    return set_err(P, SPG_E_INVAL, "lambda and mu must be finite and >= 0");
+  P->prm.lambda = lambda;
+  P->prm.mu = mu;
+  recompute_L(P);
+  restart(P);
+  return SPG_OK;
+}
+
+spg_status spg_set_map(spg_problem* P, const float* d_x0) {
+  spg_status s = usable(P);
+  if (s) return s;
+  SPG_CK(P, launch_set_map(P->d, d_x0, P->xhi(P->cur), P->xlo(P->cur), P->stream));
+  restart(P);
+  return SPG_OK;
+}
+
+spg_status spg_run(spg_problem* P, int32_t K, spg_stats* stats) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if (K < 0) return set_err(P, SPG_E_INVAL, "K must be >= 0");
+  if (!P->data_set) return set_err(P, SPG_E_STATE, "spg_set_data has not succeeded");
+  if (!(P->L > 0)) return set_err(P, SPG_E_STATE, "L = 0");
+  const Dims& d = P->d;
+  for (int it = 0; it < K; ++it) {
+    if (!P->primed) {
+      SPG_CK(P, launch_prime(d, P->rbuf(), P->xhi(P->cur), P->xlo(P->cur), P->xhi(P->old), P->xlo(P->old),
+                             P->m_cur, P->m_cur != 0.0, P->comp, P->stream));
+      if ((s = r2c(P))) return s;
+      P->primed = true;
+    }
+    if ((s = gradient_pipeline(P, false, nullptr, nullptr))) return s;
+    const double t_next = P->prm.accel ? 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * P->t * P->t)) : 1.0;
+    const double m_next = P->prm.accel ? (P->t - 1.0) / t_next : 0.0;
+    const int nxt = 3 - P->cur - P->old;
+    ProxArgs a = prox_args(P, nxt, P->m_cur, m_next);
+    prof_begin(P, SPG_KERNEL_PROX_TV);
+    SPG_CK(P, launch_prox_tv(d, a, P->comp, false, P->stream));
+    prof_end(P, SPG_KERNEL_PROX_TV);
+    if ((s = r2c(P))) return s;
+    P->old = P->cur;
+    P->cur = nxt;
+    P->t = t_next;
+    P->m_cur = m_next;
+    ++P->j;
+    ++P->iters_done;
+  }
+  if (stats) {
+    stats->iters_done = P->iters_done;
+    stats->round = P->round;
+    stats->iter_in_round = P->j - 1;
+    stats->lr = P->lr;
+    stats->L = P->L;
+  }
+  return SPG_OK;
+}
+
+spg_status spg_reweight(spg_problem* P, double eps1, double eps2) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if (!std::isfinite(eps1) || !std::isfinite(eps2) || eps1 <= 0 || eps2 <= 0)
+    return set_err(P, SPG_E_INVAL, "eps1 and eps2 must be finite and > 0");
+  SPG_CK(P, launch_reweight(P->d, P->xhi(P->cur), P->xlo(P->cur), P->at<float>(P->lay.u), P->at<float>(P->lay.v),
+                            eps1, eps2, P->comp, P->part(), kStatBlocks, P->stream));
+  const int ops[1] = {RED_OP_MAX};
+  SPG_CK(P, launch_reduce(P->part(), kStatBlocks, 1, ops, P->res(), P->stream));
+  double vmax;
+  if ((s = read_results(P, &vmax, 1))) return s;
+  P->unif_u = false;
+  P->unif_v = false;
+  P->vmax = vmax;
+  ++P->round;
+  recompute_L(P);
+  restart(P);
+  return SPG_OK;
+}
+
+spg_status spg_get_map(spg_problem* P, float* d_x_out) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if (!d_x_out) return set_err(P, SPG_E_INVAL, "output pointer is NULL");
+  SPG_CK(P, launch_get_map(P->d, P->xhi(P->cur), P->xlo(P->cur), d_x_out, P->comp, P->stream));
+  return SPG_OK;
+}
+
+spg_status spg_get_penalty_weights(spg_problem* P, float* d_u_out, float* d_v_out) {
+  spg_status s = usable(P);
+  if (s) return s;
+  const size_t bytes = (size_t)P->d.nvox * 4;
+  if (d_u_out) {
+    if (P->unif_u) SPG_CK(P, launch_fill(d_u_out, P->d.nvox, 1.0f, P->stream));
+    else SPG_CK(P, hipMemcpyAsync(d_u_out, P->at<float>(P->lay.u), bytes, hipMemcpyDeviceToDevice, P->stream));
+  }
+  if (d_v_out) {
+    if (P->unif_v) SPG_CK(P, launch_fill(d_v_out, P->d.nvox, 1.0f, P->stream));
+    else SPG_CK(P, hipMemcpyAsync(d_v_out, P->at<float>(P->lay.v), bytes, hipMemcpyDeviceToDevice, P->stream));
+  }
+  return SPG_OK;
+}
+
+spg_status spg_final_check(spg_problem* P, double* F_eps, double* F_0, double* kkt_rel) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if (!P->data_set) return set_err(P, SPG_E_STATE, "spg_set_data has not succeeded");
+  const Dims& d = P->d;
+  SPG_CK(P, launch_prime(d, P->rbuf(), P->xhi(P->cur), P->xlo(P->cur), nullptr, nullptr, 0.0, 0, P->comp, P->stream));
+  P->primed = false;
+  if ((s = r2c(P))) return s;
+  int nA = 0, nB = 0;
+  if ((s = gradient_pipeline(P, true, &nA, &nB))) return s;
+  ProxArgs a = prox_args(P, P->cur, 0.0, 0.0);
+  a.read_old = 0;
+  const int nC = prox_num_blocks(d);
+  a.partials = P->part() + kPartC;
+  SPG_CK(P, launch_prox_tv(d, a, P->comp, true, P->stream));
+  const int sum1[1] = {RED_OP_SUM};
+  const int sum5[5] = {RED_OP_SUM, RED_OP_SUM, RED_OP_SUM, RED_OP_SUM, RED_OP_SUM};
+  SPG_CK(P, launch_reduce(P->part() + kPartA, nA, 1, sum1, P->res() + 0, P->stream));
+  SPG_CK(P, launch_reduce(P->part() + kPartB, nB, 1, sum1, P->res() + 1, P->stream));
+  SPG_CK(P, launch_reduce(P->part() + kPartC, nC, 5, sum5, P->res() + 2, P->stream));
+  double r[7];
+  if ((s = read_results(P, r, 7))) return s;
+  const double data = P->C0 + r[0] + r[1];
+  const double fe = data + P->prm.lambda * r[2] + P->prm.mu * r[3];
+  const double f0 = data + P->prm.lambda * r[2] + P->prm.mu * r[4];
+  const double kkt = std::sqrt(r[5]) / (r[6] > 0 ? std::sqrt(r[6]) : 1.0);
+  if (F_eps) *F_eps = fe;
+  if (F_0) *F_0 = f0;
+  if (kkt_rel) *kkt_rel = kkt;
+  if (!std::isfinite(fe)) return set_err(P, SPG_E_DIVERGED, "objective is not finite");
+  return SPG_OK;
+}
+
+// ---------------------------------------------------------------- checkpoints
+
+struct StateHeader {
+  uint64_t magic;
+  int32_t nx, ny, nz, flags;
+  int32_t unif_u, unif_v, j, round;
+  int64_t iters_done;
+  double t, m_cur, vmax, lambda, mu, eps;
+};
+
+static size_t state_bytes(const spg_problem* P) {
+  const size_t nvox = (size_t)P->d.nvox;
+  const size_t slot = align_up(nvox * 4) + (P->comp ? align_up(nvox * 2) : 0);
+  return kAlign + 2 * slot + 2 * align_up(nvox * 4);
+}
+
+spg_status spg_state_size(const spg_problem* P, size_t* bytes) {
+  if (!P || !bytes) return SPG_E_INVAL;
+  *bytes = state_bytes(P);
+  return SPG_OK;
+}
+
+spg_status spg_get_state(spg_problem* P, void* d_buf, size_t bytes) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if (!d_buf || bytes < state_bytes(P)) return set_err(P, SPG_E_INVAL, "state buffer too small or NULL");
+  StateHeader h{};
+  h.magic = kStateMagic;
+  h.nx = P->d.nx; h.ny = P->d.ny; h.nz = P->d.nz; h.flags = P->prm.flags;
+  h.unif_u = P->unif_u; h.unif_v = P->unif_v; h.j = P->j; h.round = P->round;
+  h.iters_done = P->iters_done;
+  h.t = P->t; h.m_cur = P->m_cur; h.vmax = P->vmax;
+  h.lambda = P->prm.lambda; h.mu = P->prm.mu; h.eps = P->prm.eps;
+  char* dst = reinterpret_cast<char*>(d_buf);
+  const size_t nvox = (size_t)P->d.nvox;
+  size_t off = kAlign;
+  const int slots[2] = {P->cur, P->old};
+  for (int k = 0; k < 2; ++k) {
+    SPG_CK(P, hipMemcpyAsync(dst + off, P->xhi(slots[k]), nvox * 4, hipMemcpyDeviceToDevice, P->stream));
+    off += align_up(nvox * 4);
+    if (P->comp) {
+      SPG_CK(P, hipMemcpyAsync(dst + off, P->xlo(slots[k]), nvox * 2, hipMemcpyDeviceToDevice, P->stream));
+      off += align_up(nvox * 2);
+    }
+  }
+  if (!P->unif_u) SPG_CK(P, hipMemcpyAsync(dst + off, P->at<float>(P->lay.u), nvox * 4, hipMemcpyDeviceToDevice, P->stream));
+  off += align_up(nvox * 4);
+  if (!P->unif_v) SPG_CK(P, hipMemcpyAsync(dst + off, P->at<float>(P->lay.v), nvox * 4, hipMemcpyDeviceToDevice, P->stream));
+  SPG_CK(P, hipMemcpyAsync(dst, &h, sizeof(h), hipMemcpyHostToDevice, P->stream));
+  SPG_CK(P, hipStreamSynchronize(P->stream));
+  return SPG_OK;
+}
+
+spg_status spg_set_state(spg_problem* P, const void* d_buf, size_t bytes) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if (!d_buf || bytes < state_bytes(P)) return set_err(P, SPG_E_INVAL, "state buffer too small or NULL");
+  StateHeader h{};
+  SPG_CK(P, hipMemcpyAsync(&h, d_buf, sizeof(h), hipMemcpyDeviceToHost, P->stream));
+  SPG_CK(P, hipStreamSynchronize(P->stream));
+  if (h.magic != kStateMagic || h.nx != P->d.nx || h.ny != P->d.ny || h.nz != P->d.nz || h.flags != P->prm.flags)
+    return set_err(P, SPG_E_INVAL, "state buffer does not match this problem");
+  const char* src = reinterpret_cast<const char*>(d_buf);
+  const size_t nvox = (size_t)P->d.nvox;
+  size_t off = kAlign;
+  const int slots[2] = {0, 1};
+  for (int k = 0; k < 2; ++k) {
+    SPG_CK(P, hipMemcpyAsync(P->xhi(slots[k]), src + off, nvox * 4, hipMemcpyDeviceToDevice, P->stream));
+    off += align_up(nvox * 4);
+    if (P->comp) {
+      SPG_CK(P, hipMemcpyAsync(P->xlo(slots[k]), src + off, nvox * 2, hipMemcpyDeviceToDevice, P->stream));
+      off += align_up(nvox * 2);
+    }
+  }
+  if (!h.unif_u) SPG_CK(P, hipMemcpyAsync(P->at<float>(P->lay.u), src + off, nvox * 4, hipMemcpyDeviceToDevice, P->stream));
+  off += align_up(nvox * 4);
+  if (!h.unif_v) SPG_CK(P, hipMemcpyAsync(P->at<float>(P->lay.v), src + off, nvox * 4, hipMemcpyDeviceToDevice, P->stream));
+  P->cur = 0;
+  P->old = 1;
+  P->unif_u = h.unif_u != 0;
+  P->unif_v = h.unif_v != 0;
+  P->j = h.j;
+  P->round = h.round;
+  P->iters_done = h.iters_done;
+  P->t = h.t;
+  P->m_cur = h.m_cur;
+  P->vmax = h.vmax;
+  P->prm.lambda = h.lambda;
+  P->prm.mu = h.mu;
+  P->prm.eps = h.eps;
+  P->primed = false;
+  recompute_L(P);
+  return SPG_OK;
+}
+
+// ---------------------------------------------------------------- profiling
+
+spg_status spg_profile_begin(spg_problem* P, int32_t kernel_class, int32_t capacity) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if (kernel_class < 0 || kernel_class >= SPG_KERNEL_COUNT || capacity <= 0 || capacity > (1 << 20))
+    return set_err(P, SPG_E_INVAL, "bad kernel class or capacity");
+  for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
+  P->ev.assign(2 * (size_t)capacity, nullptr);
+  for (auto& e : P->ev) SPG_CK(P, hipEventCreate(&e));
+  P->prof_class = kernel_class;
+  P->prof_cap = capacity;
+  P->prof_n = 0;
+  return SPG_OK;
+}
+
+spg_status spg_profile_end(spg_problem* P, double* total_ms, int32_t* launches) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if (P->prof_class < 0) return set_err(P, SPG_E_STATE, "profiling is not enabled");
+  SPG_CK(P, hipStreamSynchronize(P->stream));
+  double tot = 0;
+  for (int k = 0; k < P->prof_n; ++k) {
+    float ms = 0;
+    SPG_CK(P, hipEventElapsedTime(&ms, P->ev[2 * k], P->ev[2 * k + 1]));
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = P->prof_n;
+  for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
+  P->ev.clear();
+  P->prof_class = -1;
+  P->prof_cap = 0;
+  P->prof_n = 0;
+  return SPG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// Internal interface between the host runtime (spg_api.hip) and the gfx950 kernels
+// (spg_kernels.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spg {
+
+// Grid geometry.  Real maps are nz*ny*nx floats, C order, x fastest.  The half spectrum
+// of a real map is stored packed: rows of P = nx/2 complex values per (z, y) with the
+// purely real kx = 0 and kx = nx/2 values of the x-axis real FFT sharing slot 0
+// (re = kx 0, im = kx nx/2); the y and z transforms act on that packed slot linearly and
+// the Fourier weight step separates the two planes again using Hermitian symmetry.
+struct Dims {
+  int nx, ny, nz, P;
+  long long nvox;
+};
+
+// Tile of the fused stencil / prox kernel: 64 x-columns by 8 y-rows, marched along z.
+constexpr int PT_TX = 64;
+constexpr int PT_TY = 8;
+constexpr int PT_ZC = 32;
+
+// Reductions: per-block fp64 partials, summed in fixed order by k_reduce.
+constexpr int RED_OP_SUM = 0, RED_OP_MAX = 1, RED_OP_MIN = 2;
+
+// Arguments of the fused stencil / prox kernel.
+struct ProxArgs {
+  float* rbuf;                  // in: data gradient of y_k (real map); out: y_{k+1}
+  const float* xk_hi;           // x_k  (fp32 hi part)
+  const uint16_t* xk_lo;        // x_k  (bf16 lo part; compensated mode only)
+  const float* xo_hi;           // x_{k-1}
+  const uint16_t* xo_lo;
+  float* xn_hi;                 // x_{k+1}
+  uint16_t* xn_lo;
+  const float* u;               // l1 weights or nullptr (uniform 1)
+  const float* v;               // TV weights or nullptr (uniform 1)
+  double* partials;             // check mode: 5 x nblocks fp64 partials
+  int nx, ny, nz;
+  int read_old;                 // 0 when m == 0: x_{k-1} is not read
+  double m, m_next;             // momentum for y_k and for y_{k+1}
+  double lr, lam, mu;
+  float eps;
+};
+
+int prox_num_blocks(const Dims& d);
+
+hipError_t launch_fft_cols(const Dims& d, float2* S, int axis /*1 = y, 2 = z*/, int mode,
+                           const float2* tw, const float* ws, const float2* cs, double* partials,
+                           hipStream_t st, int* nblocks_out);
+hipError_t launch_dc_nyquist(const Dims& d, float2* S, const float2* tw_z, const float* ws,
+                             const float* wnyq, const float2* cs, const float2* cnyq, double* partials,
+                             hipStream_t st, int* nblocks_out);
+hipError_t launch_r2c_x(const Dims& d, const float* rin, float2* S, const float2* tw_m,
+                        const float2* tw_n, hipStream_t st);
+hipError_t launch_c2r_x(const Dims& d, const float2* S, float* rout, const float2* tw_m,
+                        const float2* tw_n, hipStream_t st);
+hipError_t launch_prox_tv(const Dims& d, const ProxArgs& a, bool compensated, bool check, hipStream_t st);
+
+hipError_t launch_prime(const Dims& d, float* rbuf, const float* xk_hi, const uint16_t* xk_lo,
+                        const float* xo_hi, const uint16_t* xo_lo, double m, int read_old,
+                        bool compensated, hipStream_t st);
+hipError_t launch_set_map(const Dims& d, const float* x0, float* hi, uint16_t* lo, hipStream_t st);
+hipError_t launch_get_map(const Dims& d, const float* hi, const uint16_t* lo, float* out, bool compensated,
+                          hipStream_t st);
+hipError_t launch_fold(const Dims& d, const float* w, const float2* b, float* ws, float* wnyq, float2* cs,
+                       float2* cnyq, double* partials, int nblocks, hipStream_t st);
+hipError_t launch_data_stats(const Dims& d, const float* w, const float2* b, double* partials, int nblocks,
+                             hipStream_t st);
+hipError_t launch_weight_stats(const Dims& d, const float* a, double* partials, int nblocks, hipStream_t st);
+hipError_t launch_reweight(const Dims& d, const float* hi, const uint16_t* lo, float* u, float* v,
+                           double eps1, double eps2, bool compensated, double* partials, int nblocks,
+                           hipStream_t st);
+hipError_t launch_fill(float* dst, long long n, float value, hipStream_t st);
+hipError_t launch_reduce(const double* partials, int n, int nq, const int* ops, double* out, hipStream_t st);
+
+}  // namespace spg

@@ -1,0 +1,1000 @@
+// gfx950 kernels of the SPG solver for the reweighted weighted-l1 + TV reconstruction
+// (Luo, arXiv 1905.13408, eq 12-21 and eq 31).
+//
+// One SPG iteration crosses HBM in these sweeps (all in place on the packed half
+// spectrum S except where noted):
+//   k_fft_cols<mode 0> (y axis)   forward column FFTs along y
+//   k_fft_cols<mode 2> (z axis)   forward FFT along z, G = w~ Y - c, inverse FFT along z
+//   k_dc_nyquist                  the same for the packed kx = 0 / kx = nx/2 plane
+//   k_fft_cols<mode 1> (y axis)   inverse column FFTs along y
+//   k_c2r_x                       x-axis inverse real FFT -> data gradient map
+//   k_prox_tv                     smoothed-TV stencil, gradient step, soft threshold,
+//                                 momentum extrapolation (marches z-slabs through LDS)
+//   k_r2c_x                       x-axis forward real FFT of the next extrapolated map
+// The path is HBM-bound (a few flop per byte), so the kernels are built around
+// coalesced 128-byte row segments, LDS-resident transforms and no MFMA.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spg_internal.h"
+
+namespace spg {
+
+// ---------------------------------------------------------------- complex helpers
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+
+// bf16 <-> fp32 (round to nearest even), used for the low word of the compensated iterate.
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// ---------------------------------------------------------------- radix butterflies
+// Forward transforms use exp(-2 pi i / R), inverse ones exp(+2 pi i / R); no scaling.
+
+template <bool INV>
+__device__ __forceinline__ float2 rot_mi(float2 a) {  // a * (-i) forward, a * (+i) inverse
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft2(float2* a) {
+  float2 t = a[0];
+  a[0] = cadd(t, a[1]);
+  a[1] = csub(t, a[1]);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2* a) {
+  float2 t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+  float2 t2 = cadd(a[1], a[3]), t3 = rot_mi<INV>(csub(a[1], a[3]));
+  a[0] = cadd(t0, t2);
+  a[2] = csub(t0, t2);
+  a[1] = cadd(t1, t3);
+  a[3] = csub(t1, t3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft8(float2* a) {
+  const float s = 0.70710678118654752440f;
+  float2 e[4] = {a[0], a[2], a[4], a[6]};
+  float2 o[4] = {a[1], a[3], a[5], a[7]};
+  dft4<INV>(e);
+  dft4<INV>(o);
+  // o[k] *= W8^k
+  float2 o1 = INV ? make_float2(s * (o[1].x - o[1].y), s * (o[1].x + o[1].y))
+                  : make_float2(s * (o[1].x + o[1].y), s * (o[1].y - o[1].x));
+  float2 o2 = rot_mi<INV>(o[2]);
+  float2 o3 = INV ? make_float2(-s * (o[3].x + o[3].y), s * (o[3].x - o[3].y))
+                  : make_float2(s * (o[3].y - o[3].x), -s * (o[3].x + o[3].y));
+  a[0] = cadd(e[0], o[0]);
+  a[4] = csub(e[0], o[0]);
+  a[1] = cadd(e[1], o1);
+  a[5] = csub(e[1], o1);
+  a[2] = cadd(e[2], o2);
+  a[6] = csub(e[2], o2);
+  a[3] = cadd(e[3], o3);
+  a[7] = csub(e[3], o3);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2* a) {
+  if constexpr (R == 2) dft2<INV>(a);
+  else if constexpr (R == 4) dft4<INV>(a);
+  else dft8<INV>(a);
+}
+
+// ---------------------------------------------------------------- LDS Stockham engine
+// Length L = 2^n transform held in LDS; element p of the transform owned by this thread
+// group sits at buf[p * ps] (re and im in separate arrays).  T threads cooperate on
+// one transform (q in [0, T)).  Radix-8 stages, then one radix-4 or radix-2 stage.
+// Stage with radix R after Ns points have been combined (self-sorting Stockham form):
+// butterfly j reads j + r L/R, twiddles by exp(-+2 pi i r (j mod Ns) / (Ns R)), and
+// writes (j - j mod Ns) R + j mod Ns + r Ns.
+
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
+
+template <int L>
+struct FftPlan {
+  static constexpr int lg = ilog2c(L);
+  static constexpr int n8 = lg / 3;
+  static constexpr int rem = lg % 3;
+  static constexpr int T = (L >= 8) ? ((L / 8) < 16 ? (L / 8) : 16) : 1;
+};
+
+template <int L, int T, int R, bool INV>
+__device__ __forceinline__ void fft_stage(float* __restrict__ re, float* __restrict__ im, int ps, int q, int Ns,
+                                          const float2* __restrict__ tw) {
+  constexpr int NB = L / (R * T);
+  constexpr int STRIDE = L / R;
+  float2 a[NB][R];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = q + T * b;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int idx = (j + r * STRIDE) * ps;
+      a[b][r] = make_float2(re[idx], im[idx]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = q + T * b;
+    const int k = j & (Ns - 1);
+    if (Ns > 1) {
+      const int step = L / (Ns * R);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        float2 w = tw[r * k * step];
+        if (INV) w.y = -w.y;
+        a[b][r] = cmul(a[b][r], w);
+      }
+    }
+    dft<R, INV>(a[b]);
+    const int base = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int idx = (base + r * Ns) * ps;
+      re[idx] = a[b][r].x;
+      im[idx] = a[b][r].y;
+    }
+  }
+  __syncthreads();
+}
+
+template <int L, bool INV>
+__device__ __forceinline__ void fft_lds(float* re, float* im, int ps, int q, const float2* __restrict__ tw) {
+  using P = FftPlan<L>;
+  __syncthreads();
+  int Ns = 1;
+  if constexpr (P::n8 > 0) {
+#pragma unroll
+    for (int s = 0; s < P::n8; ++s) {
+      fft_stage<L, P::T, 8, INV>(re, im, ps, q, Ns, tw);
+      Ns *= 8;
+    }
+  }
+  if constexpr (P::rem == 2) fft_stage<L, P::T, 4, INV>(re, im, ps, q, Ns, tw);
+  if constexpr (P::rem == 1) fft_stage<L, P::T, 2, INV>(re, im, ps, q, Ns, tw);
+}
+
+// ---------------------------------------------------------------- block reductions (fp64)
+
+template <int OP>
+__device__ __forceinline__ double red_op(double a, double b) {
+  if constexpr (OP == RED_OP_SUM) return a + b;
+  else if constexpr (OP == RED_OP_MAX) return a > b ? a : b;
+  else return a < b ? a : b;
+}
+
+// Reduce one value per thread over the block in a fixed order; result valid in thread 0.
+template <int OP>
+__device__ double block_reduce(double v, double* sh) {
+  // blockDim.x is a power of two or a multiple of 64
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = (blockDim.x + 63) >> 6;
+  const int width = blockDim.x < 64 ? (int)blockDim.x : 64;
+  for (int off = width >> 1; off > 0; off >>= 1) v = red_op<OP>(v, __shfl_xor(v, off, width));
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double r = sh[0];
+  if (threadIdx.x == 0)
+    for (int w = 1; w < nw; ++w) r = red_op<OP>(r, sh[w]);
+  return r;
+}
+
+// ---------------------------------------------------------------- column FFT passes
+// Tile: NT consecutive kx columns (<= 16, one 128-byte row segment) by the whole axis.
+// mode 0: forward; mode 1: inverse; mode 2: forward, G = ws*Y - cs, inverse (z axis);
+// mode 3: as 2 and also writes per-block partials of 1/2 ws |Y|^2 - Re(conj(cs) Y)
+// (multiplicity 2 for 0 < kx < nx/2; the kx = 0 column is done by k_dc_nyquist).
+
+template <int L, int MODE>
+__global__ void __launch_bounds__(256) k_fft_cols(float2* __restrict__ S, int P, int ntiles, long long pstride,
+                                                  long long bstride, const float2* __restrict__ tw,
+                                                  const float* __restrict__ ws, const float2* __restrict__ cs,
+                                                  double* __restrict__ partials, int NT) {
+  __shared__ float s_re[L * 16];
+  __shared__ float s_im[L * 16];
+  __shared__ double s_red[8];
+  constexpr int T = FftPlan<L>::T;
+  const int tid = threadIdx.x;
+  const int c = tid % NT, q = tid / NT;
+  const int tile = blockIdx.x % ntiles;
+  const int batch = blockIdx.x / ntiles;
+  const int kx = tile * NT + c;
+  const bool valid = kx < P;
+  const long long base = (long long)batch * bstride + kx;
+  float* re = s_re + c;
+  float* im = s_im + c;
+
+  for (int p = q; p < L; p += T) {
+    float2 v = valid ? S[base + p * pstride] : make_float2(0.f, 0.f);
+    re[p * NT] = v.x;
+    im[p * NT] = v.y;
+  }
+  fft_lds<L, MODE == 1>(re, im, NT, q, tw);
+  if constexpr (MODE >= 2) {
+    double acc = 0.0;
+    for (int p = q; p < L; p += T) {
+      if (valid) {
+        const long long idx = base + p * pstride;
+        const float wv = ws[idx];
+        const float2 cv = cs[idx];
+        const float yr = re[p * NT], yi = im[p * NT];
+        if constexpr (MODE == 3) {
+          if (kx > 0)
+            acc += 2.0 * (0.5 * (double)wv * ((double)yr * yr + (double)yi * yi) -
+                          ((double)cv.x * yr + (double)cv.y * yi));
+        }
+        re[p * NT] = wv * yr - cv.x;
+        im[p * NT] = wv * yi - cv.y;
+      }
+    }
+    if constexpr (MODE == 3) {
+      double r = block_reduce<RED_OP_SUM>(acc, s_red);
+      if (tid == 0) partials[blockIdx.x] = r;
+    }
+    fft_lds<L, true>(re, im, NT, q, tw);
+  }
+  if (valid && !(MODE >= 2 && kx == 0)) {
+    for (int p = q; p < L; p += T) S[base + p * pstride] = make_float2(re[p * NT], im[p * NT]);
+  }
+}
+
+// ---------------------------------------------------------------- packed kx = 0 / nx/2 plane
+// The packed slot holds Z = X0 + i XN where X0 and XN are the (complex) yz spectra of
+// the real x-axis planes kx = 0 and kx = nx/2.  Both are Hermitian in (ky, kz), so
+// X0(k) = (Z(k) + conj Z(-k))/2 and XN(k) = (Z(k) - conj Z(-k))/(2i).  One block
+// handles the column pair ky, -ky so that every partner is on chip.
+
+template <int L, bool OBJ>
+__global__ void __launch_bounds__(256) k_dc_nyquist(float2* __restrict__ S, int P, int ny,
+                                                    const float2* __restrict__ tw, const float* __restrict__ ws,
+                                                    const float* __restrict__ wnyq, const float2* __restrict__ cs,
+                                                    const float2* __restrict__ cnyq, double* __restrict__ partials) {
+  __shared__ float s_re[L * 2];
+  __shared__ float s_im[L * 2];
+  __shared__ double s_red[8];
+  constexpr int T = FftPlan<L>::T;
+  constexpr int NE = (L + T - 1) / T;
+  const int tid = threadIdx.x;
+  const int c = tid & 1, q = tid >> 1;
+  const int ky = blockIdx.x;
+  const int kyp = (ny - ky) & (ny - 1);
+  const int myky = c == 0 ? ky : kyp;
+  const long long pstride = (long long)ny * P;
+  const long long base = (long long)myky * P;
+  float* re = s_re + c;
+  float* im = s_im + c;
+  const float* pre = s_re + (1 - c);
+  const float* pim = s_im + (1 - c);
+
+  for (int p = q; p < L; p += T) {
+    float2 v = S[base + p * pstride];
+    re[p * 2] = v.x;
+    im[p * 2] = v.y;
+  }
+  fft_lds<L, false>(re, im, 2, q, tw);
+  float2 nv[NE];
+  double acc = 0.0;
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const int kz = q + T * i;
+    if (kz < L) {
+      const int kzp = (L - kz) & (L - 1);
+      const float2 z1 = make_float2(re[kz * 2], im[kz * 2]);
+      const float2 z2 = make_float2(pre[kzp * 2], pim[kzp * 2]);
+      const float2 A = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
+      const float2 dd = make_float2(0.5f * (z1.x - z2.x), 0.5f * (z1.y + z2.y));
+      const float2 B = make_float2(dd.y, -dd.x);
+      const long long off = (long long)kz * pstride + base;
+      const long long offn = (long long)kz * ny + myky;
+      const float w0 = ws[off], wn = wnyq[offn];
+      const float2 c0 = cs[off], cn = cnyq[offn];
+      if constexpr (OBJ) {
+        if (c == 0 || ky != kyp)
+          acc += 0.5 * (double)w0 * ((double)A.x * A.x + (double)A.y * A.y) - ((double)c0.x * A.x + (double)c0.y * A.y) +
+                 0.5 * (double)wn * ((double)B.x * B.x + (double)B.y * B.y) - ((double)cn.x * B.x + (double)cn.y * B.y);
+      }
+      const float2 g0 = make_float2(w0 * A.x - c0.x, w0 * A.y - c0.y);
+      const float2 gn = make_float2(wn * B.x - cn.x, wn * B.y - cn.y);
+      nv[i] = make_float2(g0.x - gn.y, g0.y + gn.x);
+    }
+  }
+  if constexpr (OBJ) {
+    double r = block_reduce<RED_OP_SUM>(acc, s_red);
+    if (tid == 0) partials[blockIdx.x] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const int kz = q + T * i;
+    if (kz < L) {
+      re[kz * 2] = nv[i].x;
+      im[kz * 2] = nv[i].y;
+    }
+  }
+  fft_lds<L, true>(re, im, 2, q, tw);
+  if (c == 0 || ky != kyp)
+    for (int p = q; p < L; p += T) S[base + p * pstride] = make_float2(re[p * 2], im[p * 2]);
+}
+
+// ---------------------------------------------------------------- x-axis real FFTs
+// A real row of nx = 2M floats is read as M complex values z[n] = x[2n] + i x[2n+1].
+// Forward: Z = FFT_M(z), X[k] = (Z[k] + conj Z[M-k])/2 + W^k (Z[k] - conj Z[M-k])/(2i),
+// W = exp(-2 pi i / nx), packed X[0] = (X_0, X_M).  Inverse: Z[k] = E + i O with
+// E = X[k] + conj X[M-k], O = (X[k] - conj X[M-k]) conj(W^k), z = IFFT_M(Z), which is
+// the unnormalised inverse of the Hermitian row spectrum.
+// Block: NR rows; thread (row c = tid / T, q = tid % T); LDS row pitch M + 1.
+
+template <int M>
+__global__ void __launch_bounds__(256) k_r2c_x(const float* __restrict__ rin, float2* __restrict__ S, int nrows,
+                                               const float2* __restrict__ twm, const float2* __restrict__ twn,
+                                               int NR) {
+  __shared__ float s_re[(M + 1) * 16];
+  __shared__ float s_im[(M + 1) * 16];
+  constexpr int T = FftPlan<M>::T;
+  const int tid = threadIdx.x;
+  const int c = tid / T, q = tid % T;
+  const int row = blockIdx.x * NR + c;
+  const bool valid = row < nrows;
+  const float2* src = reinterpret_cast<const float2*>(rin) + (long long)row * M;
+  float* re = s_re + c * (M + 1);
+  float* im = s_im + c * (M + 1);
+  for (int p = q; p < M; p += T) {
+    float2 v = valid ? src[p] : make_float2(0.f, 0.f);
+    re[p] = v.x;
+    im[p] = v.y;
+  }
+  fft_lds<M, false>(re, im, 1, q, twm);
+  if (valid) {
+    float2* dst = S + (long long)row * M;
+    for (int k = q; k < M; k += T) {
+      const float2 zk = make_float2(re[k], im[k]);
+      float2 out;
+      if (k == 0) {
+        out = make_float2(zk.x + zk.y, zk.x - zk.y);
+      } else {
+        const float2 zm = make_float2(re[M - k], im[M - k]);
+        const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+        const float2 d = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y + zm.y));
+        const float2 o = make_float2(d.y, -d.x);
+        out = cadd(e, cmul(twn[k], o));
+      }
+      dst[k] = out;
+    }
+  }
+}
+
+template <int M>
+__global__ void __launch_bounds__(256) k_c2r_x(const float2* __restrict__ S, float* __restrict__ rout, int nrows,
+                                               const float2* __restrict__ twm, const float2* __restrict__ twn,
+                                               int NR) {
+  __shared__ float s_re[(M + 1) * 16];
+  __shared__ float s_im[(M + 1) * 16];
+  constexpr int T = FftPlan<M>::T;
+  const int tid = threadIdx.x;
+  const int c = tid / T, q = tid % T;
+  const int row = blockIdx.x * NR + c;
+  const bool valid = row < nrows;
+  const float2* src = S + (long long)row * M;
+  float* re = s_re + c * (M + 1);
+  float* im = s_im + c * (M + 1);
+  for (int k = q; k < M; k += T) {
+    float2 z = make_float2(0.f, 0.f);
+    if (valid) {
+      const float2 xk = src[k];
+      if (k == 0) {
+        z = make_float2(xk.x + xk.y, xk.x - xk.y);
+      } else {
+        const float2 xm = src[M - k];
+        const float2 e = make_float2(xk.x + xm.x, xk.y - xm.y);
+        const float2 d = make_float2(xk.x - xm.x, xk.y + xm.y);
+        const float2 o = cmulc(d, twn[k]);
+        z = make_float2(e.x - o.y, e.y + o.x);
+      }
+    }
+    re[k] = z.x;
+    im[k] = z.y;
+  }
+  fft_lds<M, true>(re, im, 1, q, twm);
+  if (valid) {
+    float2* dst = reinterpret_cast<float2*>(rout) + (long long)row * M;
+    for (int p = q; p < M; p += T) dst[p] = make_float2(re[p], im[p]);
+  }
+}
+
+// ---------------------------------------------------------------- fused stencil / prox
+// Block tile: PT_TX x-columns by PT_TY y-rows, marching z over a slab of PT_ZC planes.
+// LDS ring of two planes of the extrapolated map y (with a one-voxel halo) and two
+// planes of the weighted dual p = v Dy / max(eps, |Dy|) (eq 16 with the TV weight),
+// so that every y value crosses HBM about once per slab.  For voxel i at plane z:
+//   g_tv(i) = sum_a p_a(i) - p_a(i + e_a)                    (eq 17)
+//   z_i     = y_i - lr (g_data(i) + mu g_tv(i))              (eq 20)
+//   x_i     = sign(z_i) max(|z_i| - lr lam u_i, 0)           (eq 21)
+//   y'_i    = x_i + m' (x_i - x_k,i)                         (momentum)
+// Compensated mode: x is stored as fp32 hi + bf16 lo and the step, prox and momentum
+// are evaluated in fp64; the stencil and the FFT see y rounded to fp32.
+// Check mode: y = x_k, nothing is written except per-block fp64 partials of
+// lam sum u|x|, mu sum v huber(|Dx|), mu sum v |Dx|, |x - T(x)|^2 and |x|^2.
+
+template <bool COMP>
+__device__ __forceinline__ double load_x(const float* __restrict__ hi, const uint16_t* __restrict__ lo, long long i) {
+  if constexpr (COMP) return (double)hi[i] + (double)bf16_to_f32(lo[i]);
+  else return (double)hi[i];
+}
+
+template <bool COMP>
+__device__ __forceinline__ void eval_y(const ProxArgs& a, long long i, double& y, double& xk) {
+  if constexpr (COMP) {
+    xk = load_x<true>(a.xk_hi, a.xk_lo, i);
+    y = xk;
+    if (a.read_old) {
+      const double xo = load_x<true>(a.xo_hi, a.xo_lo, i);
+      y = xk + a.m * (xk - xo);
+    }
+  } else {
+    const float xf = a.xk_hi[i];
+    float yf = xf;
+    if (a.read_old) {
+      const float xo = a.xo_hi[i];
+      yf = xf + (float)a.m * (xf - xo);
+    }
+    xk = xf;
+    y = yf;
+  }
+}
+
+template <bool COMP, bool CHECK>
+__global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
+  constexpr int TX = PT_TX, TY = PT_TY;
+  constexpr int YW = TX + 2, YH = TY + 2;  // y plane with halo
+  constexpr int PW = TX + 1, PH = TY + 1;  // p plane with the +1 shell
+  __shared__ float sY[2][YH][YW];
+  __shared__ float sP[2][3][PH][PW];
+  __shared__ double s_red[8];
+
+  const int tid = threadIdx.x;
+  const int tx = tid & 63, ty = tid >> 6;  // owns (tx, ty) and (tx, ty + 4)
+  const int bx = blockIdx.x % ntx;
+  const int by = (blockIdx.x / ntx) % nty;
+  const int bz = blockIdx.x / (ntx * nty);
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int x0 = bx * TX, y0 = by * TY;
+  const int z0 = bz * PT_ZC;
+  const int z1 = min(z0 + PT_ZC, nz);
+  const long long plane = (long long)nx * ny;
+  const int mx = nx - 1, my = ny - 1, mz = nz - 1;
+
+  // own voxels
+  const int gx = (x0 + tx) & mx;
+  const bool vx = (x0 + tx) < nx;
+  int gy[2];
+  bool vown[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    gy[h] = (y0 + ty + 4 * h) & my;
+    vown[h] = vx && (y0 + ty + 4 * h) < ny;
+  }
+
+  double own_y[2], own_xk[2], nxt_y[2], nxt_xk[2];
+  double acc_l1 = 0.0, acc_hub = 0.0, acc_tv0 = 0.0, acc_kkt = 0.0, acc_x2 = 0.0;
+
+  auto load_plane = [&](int zz, int buf, double* ys, double* xks) {
+    const long long pz = (long long)(zz & mz) * plane;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const long long i = pz + (long long)gy[h] * nx + gx;
+      double yv, xv;
+      eval_y<COMP>(a, i, yv, xv);
+      ys[h] = yv;
+      xks[h] = xv;
+      sY[buf][ty + 4 * h + 1][tx + 1] = (float)yv;
+    }
+    if (tid < 2 * YW + 2 * TY) {
+      int lx, ly;
+      if (tid < YW) { ly = -1; lx = tid - 1; }
+      else if (tid < 2 * YW) { ly = TY; lx = tid - YW - 1; }
+      else if (tid < 2 * YW + TY) { lx = -1; ly = tid - 2 * YW; }
+      else { lx = TX; ly = tid - 2 * YW - TY; }
+      const long long i = pz + (long long)((y0 + ly) & my) * nx + ((x0 + lx) & mx);
+      double yv, xv;
+      eval_y<COMP>(a, i, yv, xv);
+      sY[buf][ly + 1][lx + 1] = (float)yv;
+    }
+  };
+
+  // p on the (TX+1) x (TY+1) points of plane zz from y planes zz (buf yn) and zz-1 (buf yp).
+  auto compute_p = [&](int zz, int yn, int yp, int dst, bool count) {
+    const long long pz = (long long)(zz & mz) * plane;
+    for (int idx = tid; idx < PW * PH; idx += 256) {
+      const int ly = idx / PW, lx = idx - ly * PW;
+      const float yc = sY[yn][ly + 1][lx + 1];
+      const float dxv = yc - sY[yn][ly + 1][lx];
+      const float dyv = yc - sY[yn][ly][lx + 1];
+      const float dzv = yc - sY[yp][ly + 1][lx + 1];
+      const float n = sqrtf(dxv * dxv + dyv * dyv + dzv * dzv);
+      const long long gi = pz + (long long)((y0 + ly) & my) * nx + ((x0 + lx) & mx);
+      const float vv = a.v ? a.v[gi] : 1.0f;
+      const float sc = vv / fmaxf(a.eps, n);
+      sP[dst][0][ly][lx] = sc * dzv;
+      sP[dst][1][ly][lx] = sc * dyv;
+      sP[dst][2][ly][lx] = sc * dxv;
+      if constexpr (CHECK) {
+        if (count && lx < TX && ly < TY && (x0 + lx) < nx && (y0 + ly) < ny) {
+          const double nd = n;
+          const double e = a.eps;
+          const double hub = nd < e ? nd * nd / (2.0 * e) : nd - 0.5 * e;
+          acc_hub += (double)vv * hub;
+          acc_tv0 += (double)vv * nd;
+        }
+      }
+    }
+  };
+
+  // prologue: planes z0-1 and z0, then p(z0)
+  {
+    double dy_[2], dx_[2];
+    load_plane(z0 - 1, 0, dy_, dx_);
+    load_plane(z0, 1, own_y, own_xk);
+  }
+  __syncthreads();
+  compute_p(z0, 1, 0, 0, true);
+  int cur = 0, ycur = 1;
+
+  for (int z = z0; z < z1; ++z) {
+    load_plane(z + 1, ycur ^ 1, nxt_y, nxt_xk);
+    __syncthreads();
+    compute_p(z + 1, ycur ^ 1, ycur, cur ^ 1, (z + 1) < z1);
+    __syncthreads();
+    const long long pz = (long long)z * plane;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int ly = ty + 4 * h, lx = tx;
+      const float gtv = sP[cur][0][ly][lx] + sP[cur][1][ly][lx] + sP[cur][2][ly][lx] - sP[cur][2][ly][lx + 1] -
+                        sP[cur][1][ly + 1][lx] - sP[cur ^ 1][0][ly][lx];
+      if (vown[h]) {
+        const long long i = pz + (long long)gy[h] * nx + gx;
+        const float gd = a.rbuf[i];
+        const float uu = a.u ? a.u[i] : 1.0f;
+        if constexpr (COMP) {
+          const double y = own_y[h];
+          const double zv = y - a.lr * ((double)gd + a.mu * (double)gtv);
+          const double t = a.lr * a.lam * (double)uu;
+          const double az = fabs(zv) - t;
+          const double xn = az > 0.0 ? copysign(az, zv) : 0.0;
+          if constexpr (CHECK) {
+            acc_l1 += (double)uu * fabs(y);
+            acc_kkt += (y - xn) * (y - xn);
+            acc_x2 += y * y;
+          } else {
+            const float hi = (float)xn;
+            const uint16_t lo = f32_to_bf16((float)(xn - (double)hi));
+            a.xn_hi[i] = hi;
+            a.xn_lo[i] = lo;
+            const double xs = (double)hi + (double)bf16_to_f32(lo);
+            const double yn = xs + a.m_next * (xs - own_xk[h]);
+            a.rbuf[i] = (float)yn;
+          }
+        } else {
+          const float y = (float)own_y[h];
+          const float zv = y - (float)a.lr * (gd + (float)a.mu * gtv);
+          const float t = (float)a.lr * (float)a.lam * uu;
+          const float az = fabsf(zv) - t;
+          const float xn = az > 0.f ? copysignf(az, zv) : 0.f;
+          if constexpr (CHECK) {
+            acc_l1 += (double)uu * fabs((double)y);
+            acc_kkt += ((double)y - xn) * ((double)y - xn);
+            acc_x2 += (double)y * y;
+          } else {
+            a.xn_hi[i] = xn;
+            const float xk = (float)own_xk[h];
+            a.rbuf[i] = xn + (float)a.m_next * (xn - xk);
+          }
+        }
+      }
+    }
+    cur ^= 1;
+    ycur ^= 1;
+    own_y[0] = nxt_y[0];
+    own_y[1] = nxt_y[1];
+    own_xk[0] = nxt_xk[0];
+    own_xk[1] = nxt_xk[1];
+  }
+  if constexpr (CHECK) {
+    const int nb = gridDim.x;
+    double r;
+    r = block_reduce<RED_OP_SUM>(acc_l1, s_red);
+    if (tid == 0) a.partials[0 * nb + blockIdx.x] = r;
+    r = block_reduce<RED_OP_SUM>(acc_hub, s_red);
+    if (tid == 0) a.partials[1 * nb + blockIdx.x] = r;
+    r = block_reduce<RED_OP_SUM>(acc_tv0, s_red);
+    if (tid == 0) a.partials[2 * nb + blockIdx.x] = r;
+    r = block_reduce<RED_OP_SUM>(acc_kkt, s_red);
+    if (tid == 0) a.partials[3 * nb + blockIdx.x] = r;
+    r = block_reduce<RED_OP_SUM>(acc_x2, s_red);
+    if (tid == 0) a.partials[4 * nb + blockIdx.x] = r;
+  }
+}
+
+// ---------------------------------------------------------------- elementwise kernels
+
+template <bool COMP>
+__global__ void k_prime(float* __restrict__ rbuf, const float* __restrict__ xk_hi, const uint16_t* __restrict__ xk_lo,
+                        const float* __restrict__ xo_hi, const uint16_t* __restrict__ xo_lo, double m, int read_old,
+                        long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    if constexpr (COMP) {
+      const double xk = load_x<true>(xk_hi, xk_lo, i);
+      double y = xk;
+      if (read_old) y = xk + m * (xk - load_x<true>(xo_hi, xo_lo, i));
+      rbuf[i] = (float)y;
+    } else {
+      const float xk = xk_hi[i];
+      float y = xk;
+      if (read_old) y = xk + (float)m * (xk - xo_hi[i]);
+      rbuf[i] = y;
+    }
+  }
+}
+
+__global__ void k_set_map(const float* __restrict__ x0, float* __restrict__ hi, uint16_t* __restrict__ lo, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    hi[i] = x0 ? x0[i] : 0.0f;
+    if (lo) lo[i] = 0;
+  }
+}
+
+template <bool COMP>
+__global__ void k_get_map(const float* __restrict__ hi, const uint16_t* __restrict__ lo, float* __restrict__ out,
+                          long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = COMP ? (float)load_x<true>(hi, lo, i) : hi[i];
+}
+
+__global__ void k_fill(float* __restrict__ dst, long long n, float value) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = value;
+}
+
+// Fold of the data term onto the packed half spectrum (a real map only sees the
+// Hermitian part of w (A x - b)):  w~ = (w_k + w_{-k})/2,  c = (w_k b_k + w_{-k} conj b_{-k})/2,
+// stored scaled for unnormalised transforms: ws = w~ / nvox, cs = c / sqrt(nvox).
+// Partial: max w~.
+__global__ void __launch_bounds__(256) k_fold(Dims d, const float* __restrict__ w, const float2* __restrict__ b,
+                                              float* __restrict__ ws, float* __restrict__ wnyq,
+                                              float2* __restrict__ cs, float2* __restrict__ cnyq,
+                                              double* __restrict__ partials) {
+  __shared__ double s_red[8];
+  const int P = d.P;
+  const long long nh = (long long)d.nz * d.ny * (P + 1);
+  const double inv_n = 1.0 / (double)d.nvox;
+  const double inv_sqrt_n = 1.0 / sqrt((double)d.nvox);
+  double mx = 0.0;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nh; t += (long long)gridDim.x * blockDim.x) {
+    const int kx = (int)(t % (P + 1));
+    const long long r = t / (P + 1);
+    const int ky = (int)(r % d.ny);
+    const int kz = (int)(r / d.ny);
+    const int nkx = (d.nx - kx) & (d.nx - 1), nky = (d.ny - ky) & (d.ny - 1), nkz = (d.nz - kz) & (d.nz - 1);
+    const long long ik = ((long long)kz * d.ny + ky) * d.nx + kx;
+    const long long in = ((long long)nkz * d.ny + nky) * d.nx + nkx;
+    const double wk = w[ik], wn = w[in];
+    const float2 bk = b[ik], bn = b[in];
+    const double wt = 0.5 * (wk + wn);
+    const double cr = 0.5 * (wk * bk.x + wn * bn.x);
+    const double ci = 0.5 * (wk * bk.y - wn * bn.y);
+    mx = wt > mx ? wt : mx;
+    if (kx < P) {
+      const long long o = ((long long)kz * d.ny + ky) * P + kx;
+      ws[o] = (float)(wt * inv_n);
+      cs[o] = make_float2((float)(cr * inv_sqrt_n), (float)(ci * inv_sqrt_n));
+    } else {
+      const long long o = (long long)kz * d.ny + ky;
+      wnyq[o] = (float)(wt * inv_n);
+      cnyq[o] = make_float2((float)(cr * inv_sqrt_n), (float)(ci * inv_sqrt_n));
+    }
+  }
+  const double r = block_reduce<RED_OP_MAX>(mx, s_red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+// Input checks and constants over the full arrays: count of non-finite w or b values,
+// min w, and 1/2 sum w |b|^2 (the constant of the data term).
+__global__ void __launch_bounds__(256) k_data_stats(long long n, const float* __restrict__ w,
+                                                    const float2* __restrict__ b, double* __restrict__ partials) {
+  __shared__ double s_red[8];
+  double bad = 0.0, mn = 1e300, c0 = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const float wv = w[i];
+    const float2 bv = b[i];
+    const bool fin = isfinite(wv) && isfinite(bv.x) && isfinite(bv.y);
+    if (!fin) bad += 1.0;
+    else {
+      mn = wv < mn ? wv : mn;
+      c0 += 0.5 * (double)wv * ((double)bv.x * bv.x + (double)bv.y * bv.y);
+    }
+  }
+  const int nb = gridDim.x;
+  double r = block_reduce<RED_OP_SUM>(bad, s_red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+  r = block_reduce<RED_OP_MIN>(mn, s_red);
+  if (threadIdx.x == 0) partials[nb + blockIdx.x] = r;
+  r = block_reduce<RED_OP_SUM>(c0, s_red);
+  if (threadIdx.x == 0) partials[2 * nb + blockIdx.x] = r;
+}
+
+// Penalty-weight checks: count of non-finite values, min and max.
+__global__ void __launch_bounds__(256) k_weight_stats(long long n, const float* __restrict__ a,
+                                                      double* __restrict__ partials) {
+  __shared__ double s_red[8];
+  double bad = 0.0, mn = 1e300, mx = -1e300;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const float v = a[i];
+    if (!isfinite(v)) bad += 1.0;
+    else {
+      mn = v < mn ? v : mn;
+      mx = v > mx ? v : mx;
+    }
+  }
+  const int nb = gridDim.x;
+  double r = block_reduce<RED_OP_SUM>(bad, s_red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+  r = block_reduce<RED_OP_MIN>(mn, s_red);
+  if (threadIdx.x == 0) partials[nb + blockIdx.x] = r;
+  r = block_reduce<RED_OP_MAX>(mx, s_red);
+  if (threadIdx.x == 0) partials[2 * nb + blockIdx.x] = r;
+}
+
+// Reweighting of eq 11 from the current map: u = 1/(|x| + eps1), v = 1/(|Dx| + eps2),
+// with |Dx| the periodic backward-difference gradient norm of eq 12.  Partial: max v.
+template <bool COMP>
+__global__ void __launch_bounds__(256) k_reweight(Dims d, const float* __restrict__ hi, const uint16_t* __restrict__ lo,
+                                                  float* __restrict__ u, float* __restrict__ v, double eps1,
+                                                  double eps2, double* __restrict__ partials) {
+  __shared__ double s_red[8];
+  double mx = 0.0;
+  const long long plane = (long long)d.nx * d.ny;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < d.nvox;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % d.nx);
+    const int y = (int)((i / d.nx) % d.ny);
+    const int z = (int)(i / plane);
+    const long long ixm = i - x + ((x - 1) & (d.nx - 1));
+    const long long iym = i + (long long)(((y - 1) & (d.ny - 1)) - y) * d.nx;
+    const long long izm = i + (long long)(((z - 1) & (d.nz - 1)) - z) * plane;
+    const double xc = load_x<COMP>(hi, lo, i);
+    const double ddx = xc - load_x<COMP>(hi, lo, ixm);
+    const double ddy = xc - load_x<COMP>(hi, lo, iym);
+    const double ddz = xc - load_x<COMP>(hi, lo, izm);
+    const double nrm = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
+    u[i] = (float)(1.0 / (fabs(xc) + eps1));
+    const float vv = (float)(1.0 / (nrm + eps2));
+    v[i] = vv;
+    mx = (double)vv > mx ? (double)vv : mx;
+  }
+  const double r = block_reduce<RED_OP_MAX>(mx, s_red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+struct RedOps {
+  int op[8];
+};
+
+// Fixed-order reduction of nq groups of n partials (group q at partials[q*n .. q*n+n)).
+__global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ partials, int n, int nq, RedOps ops,
+                                                double* __restrict__ out) {
+  __shared__ double s_red[8];
+  for (int qd = 0; qd < nq; ++qd) {
+    const int op = ops.op[qd];
+    double acc = op == RED_OP_SUM ? 0.0 : (op == RED_OP_MAX ? -1e300 : 1e300);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const double v = partials[(long long)qd * n + i];
+      acc = op == RED_OP_SUM ? acc + v : (op == RED_OP_MAX ? (v > acc ? v : acc) : (v < acc ? v : acc));
+    }
+    double r;
+    if (op == RED_OP_SUM) r = block_reduce<RED_OP_SUM>(acc, s_red);
+    else if (op == RED_OP_MAX) r = block_reduce<RED_OP_MAX>(acc, s_red);
+    else r = block_reduce<RED_OP_MIN>(acc, s_red);
+    if (threadIdx.x == 0) out[qd] = r;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+#define SPG_DISPATCH_L(Lv, CALL)        \
+  switch (Lv) {                         \
+    case 2: { constexpr int L_ = 2; CALL; break; }     \
+    case 4: { constexpr int L_ = 4; CALL; break; }     \
+    case 8: { constexpr int L_ = 8; CALL; break; }     \
+    case 16: { constexpr int L_ = 16; CALL; break; }   \
+    case 32: { constexpr int L_ = 32; CALL; break; }   \
+    case 64: { constexpr int L_ = 64; CALL; break; }   \
+    case 128: { constexpr int L_ = 128; CALL; break; } \
+    case 256: { constexpr int L_ = 256; CALL; break; } \
+    case 512: { constexpr int L_ = 512; CALL; break; } \
+    default: return hipErrorInvalidValue;              \
+  }
+
+static int tpt(int L) {
+  int t = 0;
+  switch (L) {
+    case 2: t = FftPlan<2>::T; break;
+    case 4: t = FftPlan<4>::T; break;
+    case 8: t = FftPlan<8>::T; break;
+    case 16: t = FftPlan<16>::T; break;
+    case 32: t = FftPlan<32>::T; break;
+    case 64: t = FftPlan<64>::T; break;
+    case 128: t = FftPlan<128>::T; break;
+    case 256: t = FftPlan<256>::T; break;
+    case 512: t = FftPlan<512>::T; break;
+    default: t = 0;
+  }
+  return t;
+}
+
+hipError_t launch_fft_cols(const Dims& d, float2* S, int axis, int mode, const float2* tw, const float* ws,
+                           const float2* cs, double* partials, hipStream_t st, int* nblocks_out) {
+  const int L = axis == 1 ? d.ny : d.nz;
+  const int NT = d.P < 16 ? d.P : 16;
+  const int ntiles = (d.P + NT - 1) / NT;
+  const int nbatch = axis == 1 ? d.nz : d.ny;
+  const long long pstride = axis == 1 ? (long long)d.P : (long long)d.ny * d.P;
+  const long long bstride = axis == 1 ? (long long)d.ny * d.P : (long long)d.P;
+  const int T = tpt(L);
+  if (T == 0) return hipErrorInvalidValue;
+  const dim3 grid(ntiles * nbatch), block(NT * T);
+  if (nblocks_out) *nblocks_out = ntiles * nbatch;
+#define SPG_COLS(MODE_) k_fft_cols<L_, MODE_><<<grid, block, 0, st>>>(S, d.P, ntiles, pstride, bstride, tw, ws, cs, partials, NT)
+  switch (mode) {
+    case 0: SPG_DISPATCH_L(L, SPG_COLS(0)); break;
+    case 1: SPG_DISPATCH_L(L, SPG_COLS(1)); break;
+    case 2: SPG_DISPATCH_L(L, SPG_COLS(2)); break;
+    case 3: SPG_DISPATCH_L(L, SPG_COLS(3)); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef SPG_COLS
+  return hipGetLastError();
+}
+
+hipError_t launch_dc_nyquist(const Dims& d, float2* S, const float2* tw_z, const float* ws, const float* wnyq,
+                             const float2* cs, const float2* cnyq, double* partials, hipStream_t st, int* nblocks_out) {
+  const int L = d.nz;
+  const int T = tpt(L);
+  if (T == 0) return hipErrorInvalidValue;
+  const dim3 grid(d.ny / 2 + 1), block(2 * T);
+  if (nblocks_out) *nblocks_out = d.ny / 2 + 1;
+  if (partials) {
+    SPG_DISPATCH_L(L, (k_dc_nyquist<L_, true><<<grid, block, 0, st>>>(S, d.P, d.ny, tw_z, ws, wnyq, cs, cnyq, partials)));
+  } else {
+    SPG_DISPATCH_L(L, (k_dc_nyquist<L_, false><<<grid, block, 0, st>>>(S, d.P, d.ny, tw_z, ws, wnyq, cs, cnyq, partials)));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_r2c_x(const Dims& d, const float* rin, float2* S, const float2* tw_m, const float2* tw_n,
+                        hipStream_t st) {
+  const int M = d.P;
+  const int T = tpt(M);
+  if (T == 0) return hipErrorInvalidValue;
+  const int NR = 256 / T < 16 ? 256 / T : 16;
+  const int nrows = d.ny * d.nz;
+  const dim3 grid((nrows + NR - 1) / NR), block(NR * T);
+  SPG_DISPATCH_L(M, (k_r2c_x<L_><<<grid, block, 0, st>>>(rin, S, nrows, tw_m, tw_n, NR)));
+  return hipGetLastError();
+}
+
+hipError_t launch_c2r_x(const Dims& d, const float2* S, float* rout, const float2* tw_m, const float2* tw_n,
+                        hipStream_t st) {
+  const int M = d.P;
+  const int T = tpt(M);
+  if (T == 0) return hipErrorInvalidValue;
+  const int NR = 256 / T < 16 ? 256 / T : 16;
+  const int nrows = d.ny * d.nz;
+  const dim3 grid((nrows + NR - 1) / NR), block(NR * T);
+  SPG_DISPATCH_L(M, (k_c2r_x<L_><<<grid, block, 0, st>>>(S, rout, nrows, tw_m, tw_n, NR)));
+  return hipGetLastError();
+}
+
+int prox_num_blocks(const Dims& d) {
+  const int ntx = (d.nx + PT_TX - 1) / PT_TX;
+  const int nty = (d.ny + PT_TY - 1) / PT_TY;
+  const int ntz = (d.nz + PT_ZC - 1) / PT_ZC;
+  return ntx * nty * ntz;
+}
+
+hipError_t launch_prox_tv(const Dims& d, const ProxArgs& a, bool compensated, bool check, hipStream_t st) {
+  const int ntx = (d.nx + PT_TX - 1) / PT_TX;
+  const int nty = (d.ny + PT_TY - 1) / PT_TY;
+  const dim3 grid(prox_num_blocks(d)), block(256);
+  if (compensated) {
+    if (check) k_prox_tv<true, true><<<grid, block, 0, st>>>(a, ntx, nty);
+    else k_prox_tv<true, false><<<grid, block, 0, st>>>(a, ntx, nty);
+  } else {
+    if (check) k_prox_tv<false, true><<<grid, block, 0, st>>>(a, ntx, nty);
+    else k_prox_tv<false, false><<<grid, block, 0, st>>>(a, ntx, nty);
+  }
+  return hipGetLastError();
+}
+
+static dim3 ew_grid(long long n) {
+  long long g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return dim3((unsigned)g);
+}
+
+hipError_t launch_prime(const Dims& d, float* rbuf, const float* xk_hi, const uint16_t* xk_lo, const float* xo_hi,
+                        const uint16_t* xo_lo, double m, int read_old, bool compensated, hipStream_t st) {
+  if (compensated)
+    k_prime<true><<<ew_grid(d.nvox), 256, 0, st>>>(rbuf, xk_hi, xk_lo, xo_hi, xo_lo, m, read_old, d.nvox);
+  else
+    k_prime<false><<<ew_grid(d.nvox), 256, 0, st>>>(rbuf, xk_hi, xk_lo, xo_hi, xo_lo, m, read_old, d.nvox);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_map(const Dims& d, const float* x0, float* hi, uint16_t* lo, hipStream_t st) {
+  k_set_map<<<ew_grid(d.nvox), 256, 0, st>>>(x0, hi, lo, d.nvox);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_map(const Dims& d, const float* hi, const uint16_t* lo, float* out, bool compensated,
+                          hipStream_t st) {
+  if (compensated) k_get_map<true><<<ew_grid(d.nvox), 256, 0, st>>>(hi, lo, out, d.nvox);
+  else k_get_map<false><<<ew_grid(d.nvox), 256, 0, st>>>(hi, lo, out, d.nvox);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(float* dst, long long n, float value, hipStream_t st) {
+  k_fill<<<ew_grid(n), 256, 0, st>>>(dst, n, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold(const Dims& d, const float* w, const float2* b, float* ws, float* wnyq, float2* cs,
+                       float2* cnyq, double* partials, int nblocks, hipStream_t st) {
+  k_fold<<<nblocks, 256, 0, st>>>(d, w, b, ws, wnyq, cs, cnyq, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_data_stats(const Dims& d, const float* w, const float2* b, double* partials, int nblocks,
+                             hipStream_t st) {
+  k_data_stats<<<nblocks, 256, 0, st>>>(d.nvox, w, b, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_weight_stats(const Dims& d, const float* a, double* partials, int nblocks, hipStream_t st) {
+  k_weight_stats<<<nblocks, 256, 0, st>>>(d.nvox, a, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_reweight(const Dims& d, const float* hi, const uint16_t* lo, float* u, float* v, double eps1,
+                           double eps2, bool compensated, double* partials, int nblocks, hipStream_t st) {
+  if (compensated) k_reweight<true><<<nblocks, 256, 0, st>>>(d, hi, lo, u, v, eps1, eps2, partials);
+  else k_reweight<false><<<nblocks, 256, 0, st>>>(d, hi, lo, u, v, eps1, eps2, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partials, int n, int nq, const int* ops, double* out, hipStream_t st) {
+  if (nq < 1 || nq > 8) return hipErrorInvalidValue;
+  RedOps r{};
+  for (int i = 0; i < nq; ++i) r.op[i] = ops[i];
+  k_reduce<<<1, 256, 0, st>>>(partials, n, nq, r, out);
+  return hipGetLastError();
+}
+
+}  // namespace spg

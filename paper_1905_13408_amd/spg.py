@@ -1,0 +1,257 @@
+"""Python binding of the C ABI in include/spg.h (argument marshalling only).
+
+Every step of the solver runs in the HIP library ``libspg.so`` built next to this
+file; PyTorch supplies device memory (the workspace and the caller's arrays) and
+the stream.  There is no fallback: if the library is missing or no GPU is
+present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, Structure, byref, c_char_p, c_double, c_int32, c_int64, c_size_t, c_void_p
+from dataclasses import dataclass
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspg.so")
+
+SPG_OK = 0
+STATUS_NAMES = {0: "SPG_OK", -1: "SPG_E_INVAL", -2: "SPG_E_NOMEM", -3: "SPG_E_DEVICE", -4: "SPG_E_STATE",
+                -5: "SPG_E_NONFINITE", -6: "SPG_E_DIVERGED", -7: "SPG_E_UNSUPPORTED"}
+FLAG_COMPENSATED = 1
+
+KERNELS = ["fft_y_fwd", "fft_z_weight", "dc_nyquist", "fft_y_inv", "c2r_x", "prox_tv", "r2c_x"]
+
+
+class Params(Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("lambda_", c_double), ("mu", c_double),
+                ("eps", c_double), ("gamma", c_double), ("accel", c_int32), ("flags", c_int32)]
+
+
+class Stats(Structure):
+    _fields_ = [("iters_done", c_int64), ("round", c_int32), ("iter_in_round", c_int32), ("lr", c_double),
+                ("L", c_double)]
+
+
+class SPGError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libspg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1905_13408_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = c_void_p
+    sigs = {
+        "spg_workspace_size": [POINTER(Params), POINTER(c_size_t)],
+        "spg_create": [POINTER(Params), P, c_size_t, P, POINTER(P)],
+        "spg_destroy": [P],
+        "spg_set_data": [P, P, P],
+        "spg_set_penalty_weights": [P, P, P],
+        "spg_set_params": [P, c_double, c_double],
+        "spg_set_map": [P, P],
+        "spg_run": [P, c_int32, POINTER(Stats)],
+        "spg_reweight": [P, c_double, c_double],
+        "spg_get_map": [P, P],
+        "spg_get_penalty_weights": [P, P, P],
+        "spg_final_check": [P, POINTER(c_double), POINTER(c_double), POINTER(c_double)],
+        "spg_state_size": [P, POINTER(c_size_t)],
+        "spg_get_state": [P, P, c_size_t],
+        "spg_set_state": [P, P, c_size_t],
+        "spg_profile_begin": [P, c_int32, c_int32],
+        "spg_profile_end": [P, POINTER(c_double), POINTER(c_int32)],
+    }
+    for name, args in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = c_int32
+    L.spg_status_string.argtypes = [c_int32]
+    L.spg_status_string.restype = c_char_p
+    L.spg_last_error.argtypes = [P]
+    L.spg_last_error.restype = c_char_p
+    _lib = L
+    return L
+
+
+def make_params(shape, lam, mu, eps, accel=True, compensated=True, gamma=0.0) -> Params:
+    nz, ny, nx = (int(s) for s in shape)
+    return Params(nx, ny, nz, float(lam), float(mu), float(eps), float(gamma), 1 if accel else 0,
+                  FLAG_COMPENSATED if compensated else 0)
+
+
+def workspace_size(shape, lam=0.01, mu=0.05, eps=1e-3, accel=True, compensated=True, gamma=0.0) -> int:
+    p = make_params(shape, lam, mu, eps, accel, compensated, gamma)
+    n = c_size_t(0)
+    st = lib().spg_workspace_size(byref(p), byref(n))
+    if st != SPG_OK:
+        raise SPGError(st, lib().spg_status_string(st).decode())
+    return int(n.value)
+
+
+@dataclass
+class RunStats:
+    iters_done: int
+    round: int
+    iter_in_round: int
+    lr: float
+    L: float
+
+
+def _ptr(t) -> c_void_p:
+    return c_void_p(0 if t is None else t.data_ptr())
+
+
+class SPGSolver:
+    """One SPG problem on one CUDA(HIP) device and stream.
+
+    Arrays are torch tensors on that device: maps, w, u, v as float32 (nz, ny, nx);
+    b as complex64 (nz, ny, nx), FFT order.
+    """
+
+    def __init__(self, shape, lam, mu, eps, accel=True, compensated=True, device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        self.shape = tuple(int(s) for s in shape)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.compensated = compensated
+        self._L = lib()
+        p = make_params(self.shape, lam, mu, eps, accel, compensated)
+        n = c_size_t(0)
+        self._check(self._L.spg_workspace_size(byref(p), byref(n)), None)
+        self.ws_bytes = int(n.value)
+        raw = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._raw = raw
+        self.ws = raw[off:off + self.ws_bytes]
+        h = c_void_p()
+        self._check(self._L.spg_create(byref(p), c_void_p(self.ws.data_ptr()), c_size_t(self.ws_bytes),
+                                       c_void_p(self.stream.cuda_stream), byref(h)), None)
+        self._h = h
+        self._keep = []
+
+    # ------------------------------------------------------------------ plumbing
+    def _check(self, st, h=-1):
+        if st != SPG_OK:
+            handle = self._h if h == -1 else h
+            msg = self._L.spg_last_error(handle).decode() if handle else self._L.spg_status_string(st).decode()
+            raise SPGError(st, msg)
+
+    def _dev(self, t, dtype):
+        torch = self.torch
+        if t is None:
+            return None
+        if not isinstance(t, torch.Tensor):
+            t = torch.as_tensor(t)
+        t = t.to(device=self.device, dtype=dtype).contiguous()
+        if tuple(t.shape) != self.shape:
+            raise ValueError(f"expected shape {self.shape}, got {tuple(t.shape)}")
+        return t
+
+    # ------------------------------------------------------------------ API
+    def set_data(self, w, b):
+        torch = self.torch
+        w = self._dev(w, torch.float32)
+        b = self._dev(b, torch.complex64)
+        self._check(self._L.spg_set_data(self._h, _ptr(w), _ptr(torch.view_as_real(b))))
+        self._keep = [w, b]
+
+    def set_penalty_weights(self, u=None, v=None):
+        torch = self.torch
+        u = self._dev(u, torch.float32)
+        v = self._dev(v, torch.float32)
+        self._check(self._L.spg_set_penalty_weights(self._h, _ptr(u), _ptr(v)))
+        self._keep = [u, v]
+
+    def set_params(self, lam, mu):
+        self._check(self._L.spg_set_params(self._h, float(lam), float(mu)))
+
+    def set_map(self, x0=None):
+        x0 = self._dev(x0, self.torch.float32)
+        self._check(self._L.spg_set_map(self._h, _ptr(x0)))
+        self._keep = [x0]
+
+    def run(self, K: int) -> RunStats:
+        s = Stats()
+        self._check(self._L.spg_run(self._h, int(K), byref(s)))
+        return RunStats(s.iters_done, s.round, s.iter_in_round, s.lr, s.L)
+
+    def reweight(self, eps1, eps2):
+        self._check(self._L.spg_reweight(self._h, float(eps1), float(eps2)))
+
+    def get_map(self, out=None):
+        if out is None:
+            out = self.torch.empty(self.shape, dtype=self.torch.float32, device=self.device)
+        self._check(self._L.spg_get_map(self._h, _ptr(out)))
+        return out
+
+    def get_penalty_weights(self):
+        u = self.torch.empty(self.shape, dtype=self.torch.float32, device=self.device)
+        v = self.torch.empty_like(u)
+        self._check(self._L.spg_get_penalty_weights(self._h, _ptr(u), _ptr(v)))
+        return u, v
+
+    def final_check(self):
+        fe, f0, kk = c_double(), c_double(), c_double()
+        self._check(self._L.spg_final_check(self._h, byref(fe), byref(f0), byref(kk)))
+        return fe.value, f0.value, kk.value
+
+    def state_size(self) -> int:
+        n = c_size_t(0)
+        self._check(self._L.spg_state_size(self._h, byref(n)))
+        return int(n.value)
+
+    def get_state(self):
+        buf = self.torch.empty(self.state_size(), dtype=self.torch.uint8, device=self.device)
+        self._check(self._L.spg_get_state(self._h, _ptr(buf), c_size_t(buf.numel())))
+        return buf
+
+    def set_state(self, buf):
+        self._check(self._L.spg_set_state(self._h, _ptr(buf), c_size_t(buf.numel())))
+
+    def profile_begin(self, kernel: str, capacity: int):
+        self._check(self._L.spg_profile_begin(self._h, KERNELS.index(kernel), int(capacity)))
+
+    def profile_end(self):
+        ms, n = c_double(), c_int32()
+        self._check(self._L.spg_profile_end(self._h, byref(ms), byref(n)))
+        return ms.value, n.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.spg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve(vol_w, vol_b, shape, lam, mu, eps, rounds, iters, eps1, eps2, accel=True, compensated=True,
+          x0=None, device="cuda") -> "SPGSolver":
+    """Reweighting schedule: round 1 with u = v = 1, then eq 11 weights before each later round."""
+    s = SPGSolver(shape, lam, mu, eps, accel=accel, compensated=compensated, device=device)
+    s.set_data(vol_w, vol_b)
+    s.set_map(x0)
+    for r in range(rounds):
+        if r > 0:
+            s.reweight(eps1, eps2)
+        s.run(iters)
+    return s

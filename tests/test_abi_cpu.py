@@ -1,0 +1,91 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared entry point,
+and validates arguments on the host before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1905_13408_amd import spg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "spg.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(spg_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(spg.LIB_PATH):
+        from paper_1905_13408_amd import build
+        build.build()
+    return spg.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings(L):
+    for code in spg.STATUS_NAMES:
+        s = L.spg_status_string(code)
+        assert s and len(s) > 1
+
+
+def _ws(shape, **kw):
+    return spg.workspace_size(shape, **kw)
+
+
+def test_workspace_size_model():
+    nz, ny, nx = 64, 32, 16
+    n = nx * ny * nz
+    b = _ws((nz, ny, nx))
+    # 3 fp32 + 3 bf16 iterate slots, u, v, spectrum, gradient map, folded weights and data
+    core = 3 * 4 * n + 3 * 2 * n + 2 * 4 * n + 4 * n + 4 * n + 2 * n + 4 * n
+    assert core <= b <= core + 2 * 1024 * 1024
+    assert _ws((nz, ny, nx), compensated=False) < b
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 4), (4, 4, 2), (1024, 4, 4), (4, 6, 4), (0, 4, 4)])
+def test_rejects_bad_grids(shape):
+    with pytest.raises(spg.SPGError) as e:
+        _ws(shape)
+    assert e.value.status == -1
+
+
+@pytest.mark.parametrize("kw,code", [(dict(lam=-1.0), -1), (dict(mu=-0.1), -1), (dict(eps=0.0), -1),
+                                     (dict(eps=float("nan")), -1), (dict(gamma=0.1), -7),
+                                     (dict(gamma=-0.1), -1)])
+def test_rejects_bad_params(kw, code):
+    with pytest.raises(spg.SPGError) as e:
+        _ws((8, 8, 8), **kw)
+    assert e.value.status == code
+
+
+def test_create_validates_before_touching_the_device(L):
+    p = spg.make_params((8, 8, 8), 0.01, 0.05, 1e-3)
+    h = ctypes.c_void_p()
+    need = _ws((8, 8, 8))
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: every case below fails validation first
+    assert L.spg_create(ctypes.byref(p), None, need, None, ctypes.byref(h)) == -1
+    assert L.spg_create(ctypes.byref(p), ctypes.c_void_p((1 << 20) + 4), need, None, ctypes.byref(h)) == -1
+    assert L.spg_create(ctypes.byref(p), fake, need - 1, None, ctypes.byref(h)) == -2
+    assert L.spg_create(ctypes.byref(p), fake, need, None, None) == -1
+    bad = spg.make_params((8, 8, 8), 0.01, 0.05, -1.0)
+    assert L.spg_create(ctypes.byref(bad), fake, need, None, ctypes.byref(h)) == -1
+    assert not h.value
+
+
+def test_null_handles_are_rejected(L):
+    assert L.spg_run(None, 1, None) == -1
+    assert L.spg_destroy(None) == -1
+    assert L.spg_set_map(None, None) == -1
+    assert L.spg_reweight(None, 0.1, 0.1) == -1
+    assert L.spg_final_check(None, None, None, None) == -1
+    assert b"NULL" in L.spg_last_error(None)

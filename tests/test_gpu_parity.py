@@ -1,0 +1,256 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the same seeded inputs.
+
+Tolerance (FP32 arithmetic with the compensated fp32-hi + bf16-lo iterate): relative L2
+<= 1e-5 of the map, the bound the method's FP32 target states.  Plain fp32 storage is
+held to the same bound only on runs short enough for it (50 iterations).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import spg_ref as O
+from paper_1905_13408_amd import spg, synth
+
+from gpu_util import announce, gpu_solver, oracle_problem, rel_l2, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _rand_inputs(shape, seed, uv=True):
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 4242]))
+    w = synth.fourier_weights(shape).astype(np.float32)
+    b = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64) * 0.3
+    u = rng.uniform(0.5, 2.0, size=shape).astype(np.float32) if uv else None
+    v = rng.uniform(0.5, 2.0, size=shape).astype(np.float32) if uv else None
+    x0 = (rng.standard_normal(shape) * 0.1).astype(np.float32)
+    return w, b, u, v, x0
+
+
+# ------------------------------------------------------------------ closed form (mu = 0)
+
+@pytest.mark.parametrize("shape", [(4, 4, 4), (8, 16, 32), (32, 16, 8), (64, 64, 64), (16, 128, 32), (4, 512, 8)])
+@pytest.mark.parametrize("compensated", [True, False])
+def test_mu0_uniform_w_is_soft_thresholded_inverse_fft(shape, compensated):
+    announce(f"mu0 closed form shape={shape} comp={compensated}")
+    rng = np.random.default_rng(np.random.SeedSequence([1, *shape]))
+    s_w = 0.37
+    b = (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)
+    u = rng.uniform(0.2, 3.0, size=shape).astype(np.float32)
+    x0 = rng.standard_normal(shape).astype(np.float32)
+    w = np.full(shape, s_w, dtype=np.float32)
+    g = gpu_solver(shape, w, b, 0.2, 0.0, 1e-3, u=u, x0=x0, compensated=compensated)
+    g.run(1)
+    x = to_np(g.get_map())
+    rb = np.real(np.fft.ifftn(b.astype(np.complex128), norm="ortho"))
+    expect = np.sign(rb) * np.maximum(np.abs(rb) - 0.2 * u.astype(np.float64) / s_w, 0)
+    assert rel_l2(x, expect) < TOL
+    # the closed form is the exact minimiser: further iterations stay there
+    g.run(4)
+    assert rel_l2(to_np(g.get_map()), expect) < TOL
+
+
+# ------------------------------------------------------------------ full iterations vs oracle
+
+def test_config1_plain_32_parity():
+    vol, c = synth.make_config(1)
+    announce("config 1 (32^3, 50 FISTA iterations, compensated)")
+    g = gpu_solver(c["shape"], vol.w, vol.b, c["lam"], c["mu"], c["eps"])
+    g.run(c["iters"])
+    x = to_np(g.get_map())
+    p = oracle_problem(vol.w, vol.b, c["lam"], c["mu"], c["eps"])
+    xo = O.spg_solve(p, c["iters"])
+    err = rel_l2(x, xo)
+    print(f"config1 rel L2 = {err:.3e}", flush=True)
+    assert err < TOL
+
+
+def test_config1_plain_fp32_storage_parity():
+    vol, c = synth.make_config(1)
+    announce("config 1 (32^3, 50 FISTA iterations, plain fp32)")
+    g = gpu_solver(c["shape"], vol.w, vol.b, c["lam"], c["mu"], c["eps"], compensated=False)
+    g.run(c["iters"])
+    p = oracle_problem(vol.w, vol.b, c["lam"], c["mu"], c["eps"])
+    err = rel_l2(to_np(g.get_map()), O.spg_solve(p, c["iters"]))
+    print(f"config1 plain fp32 rel L2 = {err:.3e}", flush=True)
+    assert err < TOL
+
+
+@pytest.mark.parametrize("shape", [(8, 4, 16), (4, 32, 8), (16, 64, 32), (32, 8, 128), (128, 8, 64)])
+def test_ragged_shapes_weighted_parity(shape):
+    announce(f"weighted u,v parity shape={shape}")
+    w, b, u, v, x0 = _rand_inputs(shape, 3)
+    lam, mu, eps = 0.02, 0.05, 1e-2
+    g = gpu_solver(shape, w, b, lam, mu, eps, u=u, v=v, x0=x0)
+    g.run(25)
+    p = oracle_problem(w, b, lam, mu, eps, u=u, v=v)
+    xo = O.spg_solve(p, 25, x0=x0.astype(np.float64))
+    err = rel_l2(to_np(g.get_map()), xo)
+    print(f"{shape} rel L2 = {err:.3e}", flush=True)
+    assert err < TOL
+
+
+def test_ista_mode_parity():
+    shape = (16, 32, 32)
+    announce("ISTA (accel=0) parity")
+    w, b, u, v, x0 = _rand_inputs(shape, 5)
+    g = gpu_solver(shape, w, b, 0.02, 0.05, 1e-2, u=u, v=v, x0=x0, accel=False)
+    g.run(30)
+    p = oracle_problem(w, b, 0.02, 0.05, 1e-2, u=u, v=v)
+    xo = O.spg_solve(p, 30, x0=x0.astype(np.float64), accel=False)
+    assert rel_l2(to_np(g.get_map()), xo) < TOL
+
+
+def test_reweighting_schedule_parity_64():
+    cfg = synth.scaled_config((64, 64, 64), iters=40)
+    vol, c = synth.make_config(cfg)
+    announce("reweighting 64^3, 3 rounds x 40")
+    g = gpu_solver(c["shape"], vol.w, vol.b, c["lam"], c["mu"], c["eps"])
+    p = oracle_problem(vol.w, vol.b, c["lam"], c["mu"], c["eps"])
+    x = np.zeros(c["shape"])
+    for r in range(3):
+        if r > 0:
+            g.reweight(c["eps1"], c["eps2"])
+            uo, vo = O.reweight(x, c["eps1"], c["eps2"])
+            ug, vg = g.get_penalty_weights()
+            assert rel_l2(to_np(ug), uo) < TOL and rel_l2(to_np(vg), vo) < TOL
+            p = oracle_problem(vol.w, vol.b, c["lam"], c["mu"], c["eps"], u=uo, v=vo)
+        g.run(c["iters"])
+        x = O.spg_solve(p, c["iters"], x0=x)
+        err = rel_l2(to_np(g.get_map()), x)
+        print(f"round {r + 1}: rel L2 = {err:.3e}", flush=True)
+        assert err < TOL
+
+
+def test_final_check_matches_oracle():
+    shape = (32, 32, 32)
+    announce("final check objective / KKT")
+    w, b, u, v, x0 = _rand_inputs(shape, 7)
+    lam, mu, eps = 0.02, 0.05, 1e-2
+    g = gpu_solver(shape, w, b, lam, mu, eps, u=u, v=v, x0=x0)
+    g.run(20)
+    fe, f0, kkt = g.final_check()
+    x = to_np(g.get_map())
+    p = oracle_problem(w, b, lam, mu, eps, u=u, v=v)
+    ofe = O.objective(x, p)
+    of0 = O.objective(x, p, smoothed=False)
+    okkt = O.kkt_residual(x, p)
+    print(f"F_eps {fe:.10e} vs {ofe:.10e}; F_0 {f0:.10e} vs {of0:.10e}; kkt {kkt:.4e} vs {okkt:.4e}", flush=True)
+    assert abs(fe - ofe) <= 1e-6 * abs(ofe)
+    assert abs(f0 - of0) <= 1e-6 * abs(of0)
+    assert abs(kkt - okkt) <= 1e-3 * okkt + 1e-7
+    # state unchanged: continuing equals an uninterrupted run
+    g.run(5)
+    h = gpu_solver(shape, w, b, lam, mu, eps, u=u, v=v, x0=x0)
+    h.run(25)
+    assert torch.equal(g.get_map(), h.get_map())
+
+
+# ------------------------------------------------------------------ properties
+
+def test_deterministic_bitwise():
+    shape = (32, 64, 64)
+    announce("determinism")
+    w, b, u, v, x0 = _rand_inputs(shape, 9)
+    outs = []
+    for _ in range(2):
+        g = gpu_solver(shape, w, b, 0.02, 0.05, 1e-2, u=u, v=v, x0=x0)
+        g.run(12)
+        g.reweight(0.01, 0.01)
+        g.run(5)
+        outs.append(g.get_map())
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_checkpoint_resume_bitwise():
+    shape = (16, 32, 64)
+    announce("checkpoint / resume")
+    w, b, u, v, x0 = _rand_inputs(shape, 11)
+    g = gpu_solver(shape, w, b, 0.02, 0.05, 1e-2, x0=x0)
+    g.run(7)
+    g.reweight(0.01, 0.01)
+    g.run(4)
+    st = g.get_state()
+    g.run(9)
+    ref = g.get_map()
+    h = gpu_solver(shape, w, b, 0.02, 0.05, 1e-2)
+    h.set_state(st)
+    h.run(9)
+    assert torch.equal(h.get_map(), ref)
+
+
+def test_sign_symmetry_and_degenerate_cases():
+    shape = (16, 16, 32)
+    announce("symmetry / K=0 / zero data / huge lambda")
+    w, b, u, v, x0 = _rand_inputs(shape, 13)
+    g1 = gpu_solver(shape, w, b, 0.02, 0.05, 1e-2, u=u, v=v)
+    g2 = gpu_solver(shape, w, -b, 0.02, 0.05, 1e-2, u=u, v=v)
+    g1.run(15)
+    g2.run(15)
+    assert torch.equal(g1.get_map(), -g2.get_map())
+    g0 = gpu_solver(shape, w, b, 0.02, 0.05, 1e-2, x0=x0)
+    g0.run(0)
+    assert torch.equal(g0.get_map().cpu(), torch.from_numpy(x0))
+    gz = gpu_solver(shape, w, np.zeros(shape, np.complex64), 0.02, 0.05, 1e-2)
+    gz.run(10)
+    assert float(gz.get_map().abs().max()) == 0.0
+    gl = gpu_solver(shape, w, b, 1e6, 0.05, 1e-2, x0=x0)
+    gl.run(3)
+    assert float(gl.get_map().abs().max()) == 0.0
+
+
+def test_input_validation_on_device():
+    shape = (8, 8, 8)
+    announce("input validation")
+    w, b, u, v, x0 = _rand_inputs(shape, 15)
+    s = spg.SPGSolver(shape, 0.01, 0.05, 1e-3)
+    with pytest.raises(spg.SPGError) as e:
+        s.run(1)
+    assert e.value.status == -4
+    wb = w.copy()
+    wb[1, 2, 3] = np.nan
+    with pytest.raises(spg.SPGError) as e:
+        s.set_data(wb, b)
+    assert e.value.status == -5
+    wn = w.copy()
+    wn[0, 0, 1] = -1.0
+    with pytest.raises(spg.SPGError) as e:
+        s.set_data(wn, b)
+    assert e.value.status == -1
+    s.set_data(w, b)
+    vb = v.copy()
+    vb[3, 3, 3] = np.inf
+    with pytest.raises(spg.SPGError) as e:
+        s.set_penalty_weights(u, vb)
+    assert e.value.status == -5
+    with pytest.raises(spg.SPGError) as e:
+        s.reweight(0.0, 0.1)
+    assert e.value.status == -1
+    s.run(2)  # the problem is still usable after rejected calls
+
+
+# ------------------------------------------------------------------ full size
+
+def test_full_size_512_one_step_vs_oracle():
+    shape = (512, 512, 512)
+    announce("512^3 one compensated step with explicit u, v vs the FP64 oracle")
+    rng = np.random.default_rng(np.random.SeedSequence([17, 512]))
+    w = synth.fourier_weights(shape).astype(np.float32)
+    b = (rng.standard_normal(shape, dtype=np.float32) + 1j * rng.standard_normal(shape, dtype=np.float32)).astype(np.complex64)
+    b *= np.float32(0.3)
+    u = rng.uniform(0.5, 2.0, size=shape).astype(np.float32)
+    v = rng.uniform(0.5, 2.0, size=shape).astype(np.float32)
+    x0 = (rng.standard_normal(shape, dtype=np.float32) * np.float32(0.1))
+    lam, mu, eps = 0.01, 0.05, 1e-3
+    g = gpu_solver(shape, w, b, lam, mu, eps, u=u, v=v, x0=x0)
+    g.run(1)
+    x = to_np(g.get_map())
+    del g
+    torch.cuda.empty_cache()
+    announce("512^3 oracle step (CPU)")
+    p = oracle_problem(w, b, lam, mu, eps, u=u, v=v)
+    xo = O.spg_solve(p, 1, x0=x0.astype(np.float64))
+    err = rel_l2(x, xo)
+    print(f"512^3 one-step rel L2 = {err:.3e}", flush=True)
+    assert err < TOL
