@@ -1,0 +1,244 @@
+"""Benchmark of the SPG reconstruction on one MI355X.
+
+One step = one whole solve of the precision-512 workload: set the data (fold and
+checks), 3 reweighting rounds x 100 SPG iterations from x = 0 (two reweights in
+between), fetch the map and run the fp64 objective / KKT check.  Inputs are resident
+in HBM before the timed region starts.  The JSON line reports SPG iterations per
+second, the per-kernel device time from HIP events recorded on the solver's stream
+during the timed steps, the roofline of the dominant kernel, and the FP64 oracle
+timed on the host cores on a bounded sample (one iteration of the same workload).
+
+  python bench.py [--steps K] [--warmup W] [--config 3] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SPG iterations/sec and HBM GB/s at 512^3 FP32 (rel. L2 ≤1e-5 vs FP64 oracle)"
+HBM_PEAK_GBPS = 8000.0
+
+
+def kernel_bytes(shape, compensated=True):
+    """Algorithmic HBM bytes per launch of each kernel class (each array read or written once).
+
+    Returned as functions of the launch kind where the traffic depends on it (the stencil
+    kernel reads x_{k-1} only when the momentum is non-zero and u, v only when explicit).
+    """
+    nz, ny, nx = shape
+    n = nx * ny * nz
+    spec = 4 * n           # packed half spectrum, complex64: nz*ny*(nx/2)*8
+    xb = 6 if compensated else 4
+    col = ny * nz
+    return {
+        "fft_y_fwd": 2 * spec,
+        "fft_z_weight": 2 * spec + spec // 2 + spec,          # S in/out, w~ (fp32), c (complex64)
+        "dc_nyquist": col * (8 + 4 + 4 + 8 + 8 + 8),           # the packed kx=0 column in/out + its weights
+        "fft_y_inv": 2 * spec,
+        "c2r_x": spec + 4 * n,
+        "r2c_x": 4 * n + spec,
+        # gradient map in, y' out, x_k in, x_{k+1} out, [x_{k-1} in], [u, v in]
+        "prox_tv": lambda momentum, explicit_uv: (4 + 4 + xb + xb + (xb if momentum else 0)
+                                                  + (8 if explicit_uv else 0)) * n,
+        "prox_tv_check": lambda explicit_uv: (4 + xb + (8 if explicit_uv else 0)) * n,
+    }
+
+
+def schedule_bytes(shape, rounds, iters, steps, compensated=True):
+    """Total algorithmic bytes per kernel class over `steps` solves of the schedule."""
+    kb = kernel_bytes(shape, compensated)
+    tot = {k: 0 for k in ["fft_y_fwd", "fft_z_weight", "dc_nyquist", "fft_y_inv", "c2r_x", "prox_tv", "r2c_x"]}
+    launches = {k: 0 for k in tot}
+    for _ in range(steps):
+        for r in range(rounds):
+            explicit = r > 0
+            for j in range(1, iters + 1):
+                for k in ["fft_y_fwd", "fft_z_weight", "dc_nyquist", "fft_y_inv", "c2r_x", "r2c_x"]:
+                    tot[k] += kb[k]
+                    launches[k] += 1
+                tot["prox_tv"] += kb["prox_tv"](j >= 3, explicit)
+                launches["prox_tv"] += 1
+            tot["r2c_x"] += kb["r2c_x"]      # priming transform at the start of each round
+            launches["r2c_x"] += 1
+        # final check: one more forward/inverse pipeline and the stencil in check mode
+        for k in ["fft_y_fwd", "fft_z_weight", "dc_nyquist", "fft_y_inv", "c2r_x", "r2c_x"]:
+            tot[k] += kb[k]
+            launches[k] += 1
+        tot["prox_tv"] += kb["prox_tv_check"](rounds > 1)
+        launches["prox_tv"] += 1
+    return tot, launches
+
+
+def iteration_bytes(shape, explicit_uv=True, compensated=True):
+    kb = kernel_bytes(shape, compensated)
+    return sum(kb[k] for k in ["fft_y_fwd", "fft_z_weight", "dc_nyquist", "fft_y_inv", "c2r_x", "r2c_x"]) + \
+        kb["prox_tv"](True, explicit_uv)
+
+
+def cpu_baseline(vol, c):
+    """The FP64 oracle, as it stands, timed for one SPG iteration of the same workload."""
+    import numpy as np
+
+    from oracle import spg_ref as O
+
+    p = O.Problem(w=vol.w.astype(np.float64), b=vol.b.astype(np.complex128), lam=c["lam"], mu=c["mu"], eps=c["eps"])
+    lr = 1.0 / O.lipschitz(p)
+    x = np.zeros(c["shape"])
+    t0 = time.perf_counter()
+    O.spg_solve(p, 1, x0=x, lr=lr)
+    dt = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"value": 1.0 / dt, "unit": "iterations/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 SPG iteration of the {c['shape'][0]}^3 workload (float64 NumPy, scipy.fft with "
+                      f"{cores} workers), {dt:.1f} s wall"}
+
+
+def copy_calibration(gib: float = 1.0, reps: int = 5):
+    """A plain device copy of known size, for scaling HBM counters (FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+
+    n = int(gib * (1 << 30)) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_each_way": n * 4, "reps": reps, "GBps_read_plus_write": 2 * n * 4 / dt / 1e9}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--iters", type=int, default=None, help="override SPG iterations per round")
+    ap.add_argument("--plain-fp32", action="store_true", help="store the iterate as plain fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="time without per-kernel HIP events")
+    ap.add_argument("--copy-calib", action="store_true", help="only run the copy kernel used to scale HBM counters")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build runs a single SPG problem per device and has no "
+              "multi-GPU path; run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    if args.copy_calib:
+        copy_calibration()
+        return
+
+    from paper_1905_13408_amd import spg, synth
+
+    t_gen = time.perf_counter()
+    vol, c = synth.make_config(args.config)
+    if args.iters:
+        c["iters"] = args.iters
+    print(f"# inputs generated in {time.perf_counter() - t_gen:.1f} s: {c['name']} {c['shape']}", file=sys.stderr,
+          flush=True)
+    shape = c["shape"]
+    compensated = not args.plain_fp32
+    w = torch.from_numpy(vol.w).cuda()
+    b = torch.from_numpy(vol.b).cuda()
+    out = torch.empty(shape, dtype=torch.float32, device="cuda")
+    solver = spg.SPGSolver(shape, c["lam"], c["mu"], c["eps"], compensated=compensated)
+    rounds, iters = c["rounds"], c["iters"]
+
+    result = {}
+
+    def step():
+        solver.set_data(w, b)
+        solver.set_penalty_weights(None, None)
+        solver.set_map(None)
+        for r in range(rounds):
+            if r > 0:
+                solver.reweight(c["eps1"], c["eps2"])
+            solver.run(iters)
+        solver.get_map(out)
+        result["check"] = solver.final_check()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("# warmup done", file=sys.stderr, flush=True)
+
+    if not args.no_profile:
+        solver.profile_begin(None, args.steps * (rounds * (iters + 1) + 2))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = solver.profile_end() if not args.no_profile else None
+    print("# timed steps done", file=sys.stderr, flush=True)
+
+    elapsed = t1 - t0
+    total_iters = rounds * iters * args.steps
+    value = total_iters / elapsed
+    it_bytes = iteration_bytes(shape, True, compensated)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{c['name']}: {shape[0]}x{shape[1]}x{shape[2]}, {c['n_blobs']} Gaussian blobs on "
+                               f"{c['n_chains']} chains, SNR {c['snr']}, lambda {c['lam']}, mu {c['mu']}, eps "
+                               f"{c['eps']}, {rounds} rounds x {iters} SPG iterations, reweight floors "
+                               f"{c['eps1']}/{c['eps2']}",
+                   "iterate_storage": "fp32 hi + bf16 lo, fp64 prox" if compensated else "fp32",
+                   "step": "set data + solve + fetch map + fp64 objective/KKT check"},
+        "ms_per_iteration": 1e3 * elapsed / total_iters,
+        "model_bytes_per_iteration": it_bytes,
+        "model_GBps": it_bytes * value / 1e9,
+        "final_objective": result["check"][0],
+        "final_kkt_rel": result["check"][2],
+    }
+    if prof is not None:
+        tot_bytes, launches = schedule_bytes(shape, rounds, iters, args.steps, compensated)
+        kern = {}
+        for k, (ms, n) in prof.items():
+            if n:
+                kern[k] = {"ms_total": ms, "launches": n, "us_avg": 1e3 * ms / n,
+                           "GBps": tot_bytes[k] / (ms * 1e-3) / 1e9 if ms > 0 else None,
+                           "model_launches": launches[k]}
+        line["kernels"] = kern
+        line["kernel_ms_per_iteration"] = sum(v["ms_total"] for v in kern.values()) / total_iters
+        dom = max(kern, key=lambda k: kern[k]["ms_total"])
+        bytes_per_launch = tot_bytes[dom] / kern[dom]["launches"]
+        t_avg = kern[dom]["ms_total"] * 1e-3 / kern[dom]["launches"]
+        ach = bytes_per_launch / t_avg / 1e9
+        line["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                            "frac": ach / HBM_PEAK_GBPS, "traffic": None,
+                            "bytes_per_launch": bytes_per_launch, "us_per_launch": t_avg * 1e6}
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (FP64 oracle, one iteration)", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(vol, c)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -161,9 +161,13 @@ typedef enum {
   SPG_KERNEL_COUNT
 } spg_kernel_class;
 
-/* Profiling: time every launch of one kernel class with HIP events recorded on the
- * problem's stream around it, for at most `capacity` launches.  spg_profile_end
- * synchronises and returns the summed device time (ms) and the launch count. */
+#define SPG_KERNEL_ALL (-1)
+
+/* Profiling: time launches with HIP events recorded on the problem's stream around each
+ * of them -- every launch of one kernel class, or of every class with SPG_KERNEL_ALL --
+ * for at most `capacity` launches per class.  spg_profile_end synchronises and writes
+ * per-class totals to total_ms[SPG_KERNEL_COUNT] (device ms) and
+ * launches[SPG_KERNEL_COUNT]; either may be NULL. */
 spg_status spg_profile_begin(spg_problem* P, int32_t kernel_class, int32_t capacity);
 spg_status spg_profile_end(spg_problem* P, double* total_ms, int32_t* launches);
 

@@ -120,8 +120,10 @@ struct spg_problem {
   double t = 1.0;        // FISTA t_j
   double m_cur = 0.0;    // momentum m_j of y_j
   char err[512] = {0};
-  // profiling
-  int prof_class = -1, prof_cap = 0, prof_n = 0;
+  // profiling: events [class][launch][begin/end]
+  bool prof_on = false;
+  int prof_class = -1, prof_cap = 0;
+  int prof_n[SPG_KERNEL_COUNT] = {0};
   std::vector<hipEvent_t> ev;
 
   template <typename T>
@@ -174,13 +176,17 @@ void restart(spg_problem* P) {
 }
 
 // Profiling hooks around one launch of kernel class cls.
+bool prof_wants(spg_problem* P, int cls) {
+  return P->prof_on && (P->prof_class == SPG_KERNEL_ALL || P->prof_class == cls) && P->prof_n[cls] < P->prof_cap;
+}
+size_t prof_slot(spg_problem* P, int cls) { return 2 * ((size_t)cls * P->prof_cap + P->prof_n[cls]); }
 void prof_begin(spg_problem* P, int cls) {
-  if (P->prof_class == cls && P->prof_n < P->prof_cap) (void)hipEventRecord(P->ev[2 * P->prof_n], P->stream);
+  if (prof_wants(P, cls)) (void)hipEventRecord(P->ev[prof_slot(P, cls)], P->stream);
 }
 void prof_end(spg_problem* P, int cls) {
-  if (P->prof_class == cls && P->prof_n < P->prof_cap) {
-    (void)hipEventRecord(P->ev[2 * P->prof_n + 1], P->stream);
-    ++P->prof_n;
+  if (prof_wants(P, cls)) {
+    (void)hipEventRecord(P->ev[prof_slot(P, cls) + 1], P->stream);
+    ++P->prof_n[cls];
   }
 }
 
@@ -631,35 +637,44 @@ spg_status spg_set_state(spg_problem* P, const void* d_buf, size_t bytes) {
 spg_status spg_profile_begin(spg_problem* P, int32_t kernel_class, int32_t capacity) {
   spg_status s = usable(P);
   if (s) return s;
-  if (kernel_class < 0 || kernel_class >= SPG_KERNEL_COUNT || capacity <= 0 || capacity > (1 << 20))
+  if (kernel_class < SPG_KERNEL_ALL || kernel_class >= SPG_KERNEL_COUNT || capacity <= 0 || capacity > (1 << 20))
     return set_err(P, SPG_E_INVAL, "bad kernel class or capacity");
   for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
-  P->ev.assign(2 * (size_t)capacity, nullptr);
-  for (auto& e : P->ev) SPG_CK(P, hipEventCreate(&e));
+  P->ev.assign(2 * (size_t)capacity * SPG_KERNEL_COUNT, nullptr);
+  const int lo = kernel_class == SPG_KERNEL_ALL ? 0 : kernel_class;
+  const int hi = kernel_class == SPG_KERNEL_ALL ? SPG_KERNEL_COUNT : kernel_class + 1;
+  for (int c = lo; c < hi; ++c)
+    for (size_t k = 0; k < 2 * (size_t)capacity; ++k)
+      SPG_CK(P, hipEventCreate(&P->ev[2 * (size_t)c * capacity + k]));
+  P->prof_on = true;
   P->prof_class = kernel_class;
   P->prof_cap = capacity;
-  P->prof_n = 0;
+  for (int c = 0; c < SPG_KERNEL_COUNT; ++c) P->prof_n[c] = 0;
   return SPG_OK;
 }
 
 spg_status spg_profile_end(spg_problem* P, double* total_ms, int32_t* launches) {
   spg_status s = usable(P);
   if (s) return s;
-  if (P->prof_class < 0) return set_err(P, SPG_E_STATE, "profiling is not enabled");
+  if (!P->prof_on) return set_err(P, SPG_E_STATE, "profiling is not enabled");
   SPG_CK(P, hipStreamSynchronize(P->stream));
-  double tot = 0;
-  for (int k = 0; k < P->prof_n; ++k) {
-    float ms = 0;
-    SPG_CK(P, hipEventElapsedTime(&ms, P->ev[2 * k], P->ev[2 * k + 1]));
-    tot += ms;
+  for (int c = 0; c < SPG_KERNEL_COUNT; ++c) {
+    double tot = 0;
+    for (int k = 0; k < P->prof_n[c]; ++k) {
+      float ms = 0;
+      const size_t slot = 2 * ((size_t)c * P->prof_cap + k);
+      SPG_CK(P, hipEventElapsedTime(&ms, P->ev[slot], P->ev[slot + 1]));
+      tot += ms;
+    }
+    if (total_ms) total_ms[c] = tot;
+    if (launches) launches[c] = P->prof_n[c];
   }
-  if (total_ms) *total_ms = tot;
-  if (launches) *launches = P->prof_n;
-  for (hipEvent_t e : P->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : P->ev)
+    if (e) (void)hipEventDestroy(e);
   P->ev.clear();
+  P->prof_on = false;
   P->prof_class = -1;
   P->prof_cap = 0;
-  P->prof_n = 0;
   return SPG_OK;
 }
 

@@ -220,13 +220,17 @@ class SPGSolver:
     def set_state(self, buf):
         self._check(self._L.spg_set_state(self._h, _ptr(buf), c_size_t(buf.numel())))
 
-    def profile_begin(self, kernel: str, capacity: int):
-        self._check(self._L.spg_profile_begin(self._h, KERNELS.index(kernel), int(capacity)))
+    def profile_begin(self, kernel: Optional[str], capacity: int):
+        """Time every launch of one kernel class (name from KERNELS) or, with None, of all classes."""
+        cls = -1 if kernel is None else KERNELS.index(kernel)
+        self._check(self._L.spg_profile_begin(self._h, cls, int(capacity)))
 
-    def profile_end(self):
-        ms, n = c_double(), c_int32()
-        self._check(self._L.spg_profile_end(self._h, byref(ms), byref(n)))
-        return ms.value, n.value
+    def profile_end(self) -> dict:
+        """{kernel name: (total device ms, launches)}."""
+        ms = (c_double * len(KERNELS))()
+        n = (c_int32 * len(KERNELS))()
+        self._check(self._L.spg_profile_end(self._h, ms, n))
+        return {k: (ms[i], n[i]) for i, k in enumerate(KERNELS)}
 
     @property
     def handle(self):
