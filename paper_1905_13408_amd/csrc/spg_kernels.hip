@@ -170,6 +170,110 @@ __device__ __forceinline__ void fft_lds(float* re, float* im, int ps, int q, con
   if constexpr (P::rem == 1) fft_stage<L, P::T, 2, INV>(re, im, ps, q, Ns, tw);
 }
 
+// Register-resident variant.  Thread q of a transform owns the points q + T i,
+// i in [0, E), E = L / T, held in a[i].  The first stage reads its butterfly inputs
+// j + r L/R = q + T (b + r L/(R T)) straight from those registers and the last stage
+// (base = j because j < Ns there) writes its outputs back to them, so a 512-point
+// transform makes two LDS round trips for three stages.  Twiddles come from a table
+// in LDS.  LDS data layout as in fft_lds (re/im planes, point stride ps).
+constexpr int reg_e(int L, int T) { return L / T; }
+
+template <int L, int TT = FftPlan<L>::T>
+struct RegPlan {
+  static constexpr int n8 = FftPlan<L>::n8;
+  static constexpr int rem = FftPlan<L>::rem;
+  static constexpr int T = TT;
+  static constexpr int E = L / T;
+  static constexpr int ns = n8 + (rem ? 1 : 0);
+  static constexpr int radix(int s) { return s < n8 ? 8 : (rem == 2 ? 4 : 2); }
+  static constexpr int span(int s) {  // Ns before stage s
+    int v = 1;
+    for (int t = 0; t < s; ++t) v *= radix(t);
+    return v;
+  }
+};
+
+template <int L, int TT, int S, bool INV>
+__device__ __forceinline__ void reg_stage(float2 (&a)[reg_e(L, TT)], float* __restrict__ re,
+                                          float* __restrict__ im, int ps, int q, const float2* __restrict__ twl) {
+  using P = RegPlan<L, TT>;
+  constexpr int R = P::radix(S);
+  constexpr int Ns = P::span(S);
+  constexpr int T = P::T;
+  constexpr int NB = L / (R * T);
+  constexpr int STR = L / R;
+  constexpr bool first = S == 0;
+  constexpr bool last = S == P::ns - 1;
+  float2 v[NB][R];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if constexpr (first) {
+        v[b][r] = a[b + r * (STR / T)];
+      } else {
+        const int idx = (q + T * b + r * STR) * ps;
+        v[b][r] = make_float2(re[idx], im[idx]);
+      }
+    }
+  }
+  if constexpr (!first && !last) __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = q + T * b;
+    const int k = j & (Ns - 1);
+    if constexpr (Ns > 1) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        // exp(+2 pi i m / L) = table[L - m]: the inverse reads other addresses than the
+        // forward, so the compiler does not keep forward twiddles live for reuse
+        const int m = r * k * (L / (Ns * R));
+        const float2 w = twl[INV ? ((L - m) & (L - 1)) : m];
+        v[b][r] = cmul(v[b][r], w);
+      }
+    }
+    dft<R, INV>(v[b]);
+    if constexpr (last) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[b + r * (STR / T)] = v[b][r];
+    } else {
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int idx = (base + r * Ns) * ps;
+        re[idx] = v[b][r].x;
+        im[idx] = v[b][r].y;
+      }
+    }
+  }
+  if constexpr (!last) __syncthreads();
+}
+
+template <int L, int TT, int S, bool INV, int SEND = RegPlan<L, TT>::ns>
+__device__ __forceinline__ void reg_stages(float2 (&a)[reg_e(L, TT)], float* re, float* im, int ps, int q,
+                                           const float2* twl) {
+  if constexpr (S < SEND) {
+    reg_stage<L, TT, S, INV>(a, re, im, ps, q, twl);
+    reg_stages<L, TT, S + 1, INV, SEND>(a, re, im, ps, q, twl);
+  }
+}
+
+// Transform the registers a[] of every thread.  Precondition: no thread still reads the
+// LDS data planes (barrier after their last use) and the twiddle table is visible.
+template <int L, bool INV, int TT = FftPlan<L>::T>
+__device__ __forceinline__ void fft_reg(float2 (&a)[reg_e(L, TT)], float* re, float* im, int ps, int q,
+                                        const float2* twl) {
+  reg_stages<L, TT, 0, INV>(a, re, im, ps, q, twl);
+}
+
+// Threads per column of the column passes: more threads for the long axes keeps the
+// per-thread state of the fused z pass (data, folded weight and data term) small
+// enough for two 512-thread blocks per CU.
+template <int L>
+struct ColT {
+  static constexpr int T = L >= 256 ? 32 : FftPlan<L>::T;
+};
+
 // ---------------------------------------------------------------- block reductions (fp64)
 
 template <int OP>
@@ -203,55 +307,84 @@ __device__ double block_reduce(double v, double* sh) {
 // (multiplicity 2 for 0 < kx < nx/2; the kx = 0 column is done by k_dc_nyquist).
 
 template <int L, int MODE>
-__global__ void __launch_bounds__(256) k_fft_cols(float2* __restrict__ S, int P, int ntiles, long long pstride,
+__global__ void __launch_bounds__(512) k_fft_cols(float2* __restrict__ S, int P, int ntiles, long long pstride,
                                                   long long bstride, const float2* __restrict__ tw,
                                                   const float* __restrict__ ws, const float2* __restrict__ cs,
                                                   double* __restrict__ partials, int NT) {
   __shared__ float s_re[L * 16];
   __shared__ float s_im[L * 16];
+  __shared__ float2 s_tw[L];
   __shared__ double s_red[8];
-  constexpr int T = FftPlan<L>::T;
+  constexpr int T = ColT<L>::T;
+  constexpr int E = RegPlan<L, T>::E;
   const int tid = threadIdx.x;
   const int c = tid % NT, q = tid / NT;
   const int tile = blockIdx.x % ntiles;
   const int batch = blockIdx.x / ntiles;
   const int kx = tile * NT + c;
   const bool valid = kx < P;
-  const long long base = (long long)batch * bstride + kx;
+  // block-uniform base pointers and 32-bit per-lane element offsets (every offset of a
+  // column is below nz*ny*P <= 2^26 elements)
+  const long long ub = (long long)batch * bstride + (long long)tile * NT;
+  float2* __restrict__ Sb = S + ub;
+  const int ps32 = (int)pstride;
+  const int off0 = c + q * ps32;
+  const int step = T * ps32;
+
+  // data loads first; the z pass issues the loads of the folded weight and data term
+  // after the first forward stage so that they are in flight during the later stages
+  float2 a[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) a[i] = valid ? Sb[off0 + i * step] : make_float2(0.f, 0.f);
+  for (int i = tid; i < L; i += blockDim.x) s_tw[i] = tw[i];
+  __syncthreads();
   float* re = s_re + c;
   float* im = s_im + c;
-
-  for (int p = q; p < L; p += T) {
-    float2 v = valid ? S[base + p * pstride] : make_float2(0.f, 0.f);
-    re[p * NT] = v.x;
-    im[p * NT] = v.y;
+  constexpr int NS = RegPlan<L, T>::ns;
+  float wv[MODE >= 2 ? E : 1];
+  float2 cv[MODE >= 2 ? E : 1];
+  if constexpr (MODE >= 2 && NS > 1) {
+    reg_stages<L, T, 0, false, 1>(a, re, im, NT, q, s_tw);
+    const float* __restrict__ wsb = ws + ub;
+    const float2* __restrict__ csb = cs + ub;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      wv[i] = valid ? wsb[off0 + i * step] : 0.f;
+      cv[i] = valid ? csb[off0 + i * step] : make_float2(0.f, 0.f);
+    }
+    reg_stages<L, T, 1, false>(a, re, im, NT, q, s_tw);
+  } else {
+    if constexpr (MODE >= 2) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        wv[i] = valid ? ws[ub + off0 + i * step] : 0.f;
+        cv[i] = valid ? cs[ub + off0 + i * step] : make_float2(0.f, 0.f);
+      }
+    }
+    fft_reg<L, MODE == 1, T>(a, re, im, NT, q, s_tw);
   }
-  fft_lds<L, MODE == 1>(re, im, NT, q, tw);
   if constexpr (MODE >= 2) {
     double acc = 0.0;
-    for (int p = q; p < L; p += T) {
-      if (valid) {
-        const long long idx = base + p * pstride;
-        const float wv = ws[idx];
-        const float2 cv = cs[idx];
-        const float yr = re[p * NT], yi = im[p * NT];
-        if constexpr (MODE == 3) {
-          if (kx > 0)
-            acc += 2.0 * (0.5 * (double)wv * ((double)yr * yr + (double)yi * yi) -
-                          ((double)cv.x * yr + (double)cv.y * yi));
-        }
-        re[p * NT] = wv * yr - cv.x;
-        im[p * NT] = wv * yi - cv.y;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const float yr = a[i].x, yi = a[i].y;
+      if constexpr (MODE == 3) {
+        if (valid && kx > 0)
+          acc += 2.0 * (0.5 * (double)wv[i] * ((double)yr * yr + (double)yi * yi) -
+                        ((double)cv[i].x * yr + (double)cv[i].y * yi));
       }
+      a[i] = make_float2(wv[i] * yr - cv[i].x, wv[i] * yi - cv[i].y);
     }
     if constexpr (MODE == 3) {
       double r = block_reduce<RED_OP_SUM>(acc, s_red);
       if (tid == 0) partials[blockIdx.x] = r;
     }
-    fft_lds<L, true>(re, im, NT, q, tw);
+    __syncthreads();  // the forward transform's last stage read the LDS planes
+    fft_reg<L, true, T>(a, re, im, NT, q, s_tw);
   }
   if (valid && !(MODE >= 2 && kx == 0)) {
-    for (int p = q; p < L; p += T) S[base + p * pstride] = make_float2(re[p * NT], im[p * NT]);
+#pragma unroll
+    for (int i = 0; i < E; ++i) Sb[off0 + i * step] = a[i];
   }
 }
 
@@ -347,24 +480,35 @@ __global__ void __launch_bounds__(256) k_r2c_x(const float* __restrict__ rin, fl
                                                int NR) {
   __shared__ float s_re[(M + 1) * 16];
   __shared__ float s_im[(M + 1) * 16];
-  constexpr int T = FftPlan<M>::T;
+  __shared__ float2 s_tw[M];
+  constexpr int T = RegPlan<M>::T;
+  constexpr int E = RegPlan<M>::E;
   const int tid = threadIdx.x;
   const int c = tid / T, q = tid % T;
   const int row = blockIdx.x * NR + c;
   const bool valid = row < nrows;
   const float2* src = reinterpret_cast<const float2*>(rin) + (long long)row * M;
+  float2 a[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) a[i] = valid ? src[q + T * i] : make_float2(0.f, 0.f);
+  for (int i = tid; i < M; i += blockDim.x) s_tw[i] = twm[i];
+  __syncthreads();
   float* re = s_re + c * (M + 1);
   float* im = s_im + c * (M + 1);
-  for (int p = q; p < M; p += T) {
-    float2 v = valid ? src[p] : make_float2(0.f, 0.f);
-    re[p] = v.x;
-    im[p] = v.y;
+  fft_reg<M, false>(a, re, im, 1, q, s_tw);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    re[q + T * i] = a[i].x;
+    im[q + T * i] = a[i].y;
   }
-  fft_lds<M, false>(re, im, 1, q, twm);
+  __syncthreads();
   if (valid) {
     float2* dst = S + (long long)row * M;
-    for (int k = q; k < M; k += T) {
-      const float2 zk = make_float2(re[k], im[k]);
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int k = q + T * i;
+      const float2 zk = a[i];
       float2 out;
       if (k == 0) {
         out = make_float2(zk.x + zk.y, zk.x - zk.y);
@@ -386,35 +530,51 @@ __global__ void __launch_bounds__(256) k_c2r_x(const float2* __restrict__ S, flo
                                                int NR) {
   __shared__ float s_re[(M + 1) * 16];
   __shared__ float s_im[(M + 1) * 16];
-  constexpr int T = FftPlan<M>::T;
+  __shared__ float2 s_tw[M];
+  constexpr int T = RegPlan<M>::T;
+  constexpr int E = RegPlan<M>::E;
   const int tid = threadIdx.x;
   const int c = tid / T, q = tid % T;
   const int row = blockIdx.x * NR + c;
   const bool valid = row < nrows;
   const float2* src = S + (long long)row * M;
+  float2 a[E];
+  float2 wk[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int k = q + T * i;
+    a[i] = valid ? src[k] : make_float2(0.f, 0.f);
+    wk[i] = twn[k];
+  }
+  for (int i = tid; i < M; i += blockDim.x) s_tw[i] = twm[i];
   float* re = s_re + c * (M + 1);
   float* im = s_im + c * (M + 1);
-  for (int k = q; k < M; k += T) {
-    float2 z = make_float2(0.f, 0.f);
-    if (valid) {
-      const float2 xk = src[k];
-      if (k == 0) {
-        z = make_float2(xk.x + xk.y, xk.x - xk.y);
-      } else {
-        const float2 xm = src[M - k];
-        const float2 e = make_float2(xk.x + xm.x, xk.y - xm.y);
-        const float2 d = make_float2(xk.x - xm.x, xk.y + xm.y);
-        const float2 o = cmulc(d, twn[k]);
-        z = make_float2(e.x - o.y, e.y + o.x);
-      }
-    }
-    re[k] = z.x;
-    im[k] = z.y;
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    re[q + T * i] = a[i].x;
+    im[q + T * i] = a[i].y;
   }
-  fft_lds<M, true>(re, im, 1, q, twm);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int k = q + T * i;
+    const float2 xk = a[i];
+    if (k == 0) {
+      a[i] = make_float2(xk.x + xk.y, xk.x - xk.y);
+    } else {
+      const float2 xm = make_float2(re[M - k], im[M - k]);
+      const float2 e = make_float2(xk.x + xm.x, xk.y - xm.y);
+      const float2 d = make_float2(xk.x - xm.x, xk.y + xm.y);
+      const float2 o = cmulc(d, wk[i]);
+      a[i] = make_float2(e.x - o.y, e.y + o.x);
+    }
+  }
+  __syncthreads();
+  fft_reg<M, true>(a, re, im, 1, q, s_tw);
   if (valid) {
     float2* dst = reinterpret_cast<float2*>(rout) + (long long)row * M;
-    for (int p = q; p < M; p += T) dst[p] = make_float2(re[p], im[p]);
+#pragma unroll
+    for (int i = 0; i < E; ++i) dst[q + T * i] = a[i];
   }
 }
 
@@ -856,7 +1016,7 @@ hipError_t launch_fft_cols(const Dims& d, float2* S, int axis, int mode, const f
   const int nbatch = axis == 1 ? d.nz : d.ny;
   const long long pstride = axis == 1 ? (long long)d.P : (long long)d.ny * d.P;
   const long long bstride = axis == 1 ? (long long)d.ny * d.P : (long long)d.P;
-  const int T = tpt(L);
+  const int T = L >= 256 ? 32 : tpt(L);
   if (T == 0) return hipErrorInvalidValue;
   const dim3 grid(ntiles * nbatch), block(NT * T);
   if (nblocks_out) *nblocks_out = ntiles * nbatch;
