@@ -598,23 +598,37 @@ __device__ __forceinline__ double load_x(const float* __restrict__ hi, const uin
   else return (double)hi[i];
 }
 
+// Raw iterate words of one voxel (x_k and, when the momentum is non-zero, x_{k-1}),
+// fetched one z-step ahead of their use.
+struct RawX {
+  float xh, oh;
+  uint16_t xl, ol;
+};
+
 template <bool COMP>
-__device__ __forceinline__ void eval_y(const ProxArgs& a, long long i, double& y, double& xk) {
+__device__ __forceinline__ void fetch_raw(const ProxArgs& a, long long i, RawX& r) {
+  r.xh = a.xk_hi[i];
+  if constexpr (COMP) r.xl = a.xk_lo[i];
+  if (a.read_old) {
+    r.oh = a.xo_hi[i];
+    if constexpr (COMP) r.ol = a.xo_lo[i];
+  }
+}
+
+// y = x_k + m (x_k - x_{k-1}) from raw words: fp64 from the compensated pair, else fp32.
+template <bool COMP>
+__device__ __forceinline__ void eval_raw(const ProxArgs& a, const RawX& r, double& y, double& xk) {
   if constexpr (COMP) {
-    xk = load_x<true>(a.xk_hi, a.xk_lo, i);
+    xk = (double)r.xh + (double)bf16_to_f32(r.xl);
     y = xk;
     if (a.read_old) {
-      const double xo = load_x<true>(a.xo_hi, a.xo_lo, i);
+      const double xo = (double)r.oh + (double)bf16_to_f32(r.ol);
       y = xk + a.m * (xk - xo);
     }
   } else {
-    const float xf = a.xk_hi[i];
-    float yf = xf;
-    if (a.read_old) {
-      const float xo = a.xo_hi[i];
-      yf = xf + (float)a.m * (xf - xo);
-    }
-    xk = xf;
+    float yf = r.xh;
+    if (a.read_old) yf = r.xh + (float)a.m * (r.xh - r.oh);
+    xk = r.xh;
     y = yf;
   }
 }
@@ -624,6 +638,8 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
   constexpr int TX = PT_TX, TY = PT_TY;
   constexpr int YW = TX + 2, YH = TY + 2;  // y plane with halo
   constexpr int PW = TX + 1, PH = TY + 1;  // p plane with the +1 shell
+  constexpr int NPP = (PW * PH + 255) / 256;
+  constexpr int NHALO = 2 * YW + 2 * TY;
   __shared__ float sY[2][YH][YW];
   __shared__ float sP[2][3][PH][PW];
   __shared__ double s_red[8];
@@ -640,57 +656,82 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
   const long long plane = (long long)nx * ny;
   const int mx = nx - 1, my = ny - 1, mz = nz - 1;
 
-  // own voxels
+  // own voxels: in-plane offsets
   const int gx = (x0 + tx) & mx;
   const bool vx = (x0 + tx) < nx;
-  int gy[2];
+  int own_off[2];
   bool vown[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    gy[h] = (y0 + ty + 4 * h) & my;
+    own_off[h] = ((y0 + ty + 4 * h) & my) * nx + gx;
     vown[h] = vx && (y0 + ty + 4 * h) < ny;
   }
+  // halo point of this thread (tid < NHALO)
+  const bool has_halo = tid < NHALO;
+  int hlx = 0, hly = 0;
+  if (tid < YW) { hly = -1; hlx = tid - 1; }
+  else if (tid < 2 * YW) { hly = TY; hlx = tid - YW - 1; }
+  else if (tid < 2 * YW + TY) { hlx = -1; hly = tid - 2 * YW; }
+  else { hlx = TX; hly = tid - 2 * YW - TY; }
+  const int halo_off = ((y0 + hly) & my) * nx + ((x0 + hlx) & mx);
+  // p points of this thread
+  int p_off[NPP];
+  bool p_ok[NPP];
+#pragma unroll
+  for (int t = 0; t < NPP; ++t) {
+    const int idx = tid + 256 * t;
+    p_ok[t] = idx < PW * PH;
+    const int ly = idx / PW, lx = idx - ly * PW;
+    p_off[t] = ((y0 + ly) & my) * nx + ((x0 + lx) & mx);
+  }
 
-  double own_y[2], own_xk[2], nxt_y[2], nxt_xk[2];
-  double acc_l1 = 0.0, acc_hub = 0.0, acc_tv0 = 0.0, acc_kkt = 0.0, acc_x2 = 0.0;
-
-  auto load_plane = [&](int zz, int buf, double* ys, double* xks) {
-    const long long pz = (long long)(zz & mz) * plane;
+  auto pz_of = [&](int zz) { return (long long)(zz & mz) * plane; };
+  auto fetch_plane = [&](int zz, RawX* own, RawX& halo, float* vv) {
+    const long long pz = pz_of(zz);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) fetch_raw<COMP>(a, pz + own_off[h], own[h]);
+    if (has_halo) fetch_raw<COMP>(a, pz + halo_off, halo);
+#pragma unroll
+    for (int t = 0; t < NPP; ++t) vv[t] = (a.v && p_ok[t]) ? a.v[pz + p_off[t]] : 1.0f;
+  };
+  auto fetch_out = [&](int zz, float* g, float* uu) {
+    const long long pz = (long long)zz * plane;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const long long i = pz + (long long)gy[h] * nx + gx;
+      g[h] = vown[h] ? a.rbuf[pz + own_off[h]] : 0.f;
+      uu[h] = (a.u && vown[h]) ? a.u[pz + own_off[h]] : 1.0f;
+    }
+  };
+  auto store_plane = [&](int buf, const RawX* own, const RawX& halo, double* ys, double* xks) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
       double yv, xv;
-      eval_y<COMP>(a, i, yv, xv);
+      eval_raw<COMP>(a, own[h], yv, xv);
       ys[h] = yv;
       xks[h] = xv;
       sY[buf][ty + 4 * h + 1][tx + 1] = (float)yv;
     }
-    if (tid < 2 * YW + 2 * TY) {
-      int lx, ly;
-      if (tid < YW) { ly = -1; lx = tid - 1; }
-      else if (tid < 2 * YW) { ly = TY; lx = tid - YW - 1; }
-      else if (tid < 2 * YW + TY) { lx = -1; ly = tid - 2 * YW; }
-      else { lx = TX; ly = tid - 2 * YW - TY; }
-      const long long i = pz + (long long)((y0 + ly) & my) * nx + ((x0 + lx) & mx);
+    if (has_halo) {
       double yv, xv;
-      eval_y<COMP>(a, i, yv, xv);
-      sY[buf][ly + 1][lx + 1] = (float)yv;
+      eval_raw<COMP>(a, halo, yv, xv);
+      sY[buf][hly + 1][hlx + 1] = (float)yv;
     }
   };
 
-  // p on the (TX+1) x (TY+1) points of plane zz from y planes zz (buf yn) and zz-1 (buf yp).
-  auto compute_p = [&](int zz, int yn, int yp, int dst, bool count) {
-    const long long pz = (long long)(zz & mz) * plane;
-    for (int idx = tid; idx < PW * PH; idx += 256) {
+  double acc_l1 = 0.0, acc_hub = 0.0, acc_tv0 = 0.0, acc_kkt = 0.0, acc_x2 = 0.0;
+  // p on the (TX+1) x (TY+1) points of a plane from y planes yn (this plane) and yp (below).
+  auto compute_p = [&](int yn, int yp, int dst, const float* vv, bool count) {
+#pragma unroll
+    for (int t = 0; t < NPP; ++t) {
+      if (!p_ok[t]) continue;
+      const int idx = tid + 256 * t;
       const int ly = idx / PW, lx = idx - ly * PW;
       const float yc = sY[yn][ly + 1][lx + 1];
       const float dxv = yc - sY[yn][ly + 1][lx];
       const float dyv = yc - sY[yn][ly][lx + 1];
       const float dzv = yc - sY[yp][ly + 1][lx + 1];
       const float n = sqrtf(dxv * dxv + dyv * dyv + dzv * dzv);
-      const long long gi = pz + (long long)((y0 + ly) & my) * nx + ((x0 + lx) & mx);
-      const float vv = a.v ? a.v[gi] : 1.0f;
-      const float sc = vv / fmaxf(a.eps, n);
+      const float sc = vv[t] / fmaxf(a.eps, n);
       sP[dst][0][ly][lx] = sc * dzv;
       sP[dst][1][ly][lx] = sc * dyv;
       sP[dst][2][ly][lx] = sc * dxv;
@@ -699,27 +740,45 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
           const double nd = n;
           const double e = a.eps;
           const double hub = nd < e ? nd * nd / (2.0 * e) : nd - 0.5 * e;
-          acc_hub += (double)vv * hub;
-          acc_tv0 += (double)vv * nd;
+          acc_hub += (double)vv[t] * hub;
+          acc_tv0 += (double)vv[t] * nd;
         }
       }
     }
   };
 
-  // prologue: planes z0-1 and z0, then p(z0)
+  // ---- prologue: planes z0-1 and z0 into LDS, p(z0), and the first prefetches
+  RawX rown[2], rhalo;
+  float rv[NPP];
+  double own_y[2], own_xk[2], nxt_y[2], nxt_xk[2];
+  float g_cur[2], u_cur[2];
   {
     double dy_[2], dx_[2];
-    load_plane(z0 - 1, 0, dy_, dx_);
-    load_plane(z0, 1, own_y, own_xk);
+    fetch_plane(z0 - 1, rown, rhalo, rv);
+    store_plane(0, rown, rhalo, dy_, dx_);
+    fetch_plane(z0, rown, rhalo, rv);
+    store_plane(1, rown, rhalo, own_y, own_xk);
   }
+  fetch_out(z0, g_cur, u_cur);
   __syncthreads();
-  compute_p(z0, 1, 0, 0, true);
+  compute_p(1, 0, 0, rv, true);
+  fetch_plane(z0 + 1, rown, rhalo, rv);
   int cur = 0, ycur = 1;
 
   for (int z = z0; z < z1; ++z) {
-    load_plane(z + 1, ycur ^ 1, nxt_y, nxt_xk);
+    // y of plane z+1 from the words fetched during the previous step
+    store_plane(ycur ^ 1, rown, rhalo, nxt_y, nxt_xk);
+    float vv_use[NPP];
+#pragma unroll
+    for (int t = 0; t < NPP; ++t) vv_use[t] = rv[t];
+    float g_use[2] = {g_cur[0], g_cur[1]}, u_use[2] = {u_cur[0], u_cur[1]};
+    // prefetch plane z+2 and the outputs' inputs of plane z+1
+    if (z + 1 < z1) {
+      fetch_plane(z + 2, rown, rhalo, rv);
+      fetch_out(z + 1, g_cur, u_cur);
+    }
     __syncthreads();
-    compute_p(z + 1, ycur ^ 1, ycur, cur ^ 1, (z + 1) < z1);
+    compute_p(ycur ^ 1, ycur, cur ^ 1, vv_use, (z + 1) < z1);
     __syncthreads();
     const long long pz = (long long)z * plane;
 #pragma unroll
@@ -728,9 +787,9 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
       const float gtv = sP[cur][0][ly][lx] + sP[cur][1][ly][lx] + sP[cur][2][ly][lx] - sP[cur][2][ly][lx + 1] -
                         sP[cur][1][ly + 1][lx] - sP[cur ^ 1][0][ly][lx];
       if (vown[h]) {
-        const long long i = pz + (long long)gy[h] * nx + gx;
-        const float gd = a.rbuf[i];
-        const float uu = a.u ? a.u[i] : 1.0f;
+        const long long i = pz + own_off[h];
+        const float gd = g_use[h];
+        const float uu = u_use[h];
         if constexpr (COMP) {
           const double y = own_y[h];
           const double zv = y - a.lr * ((double)gd + a.mu * (double)gtv);
