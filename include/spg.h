@@ -10,6 +10,7 @@
  *   min_x  1/2 sum_k w_k |(A x)_k - b_k|^2            data term, A = unitary 3D DFT
  *        + lambda sum_i u_i |x_i|                      weighted l1        [alpha, w'_j]
  *        + mu     sum_i v_i phi_eps(|(D x)_i|_2)       weighted smoothed TV [beta, w_j, mu]
+ *        + gamma  |x - x_prev|^2                       implicit-descent term of eq 22
  *
  * x is a real nz*ny*nx map in C order (x fastest).  D is the backward difference
  * of eq 12 with periodic wrap; phi_eps is the per-voxel value of eq 14
@@ -17,10 +18,10 @@
  * Beck-Teboulle momentum) is
  *
  *   y   = x_k + m_k (x_k - x_{k-1})
- *   z   = y - lr (Re A^H(w (A y - b)) + mu D^T(v * Dy / max(eps, |Dy|)))
+ *   z   = y - lr (Re A^H(w (A y - b)) + mu D^T(v * Dy / max(eps, |Dy|)) + 2 gamma (y - x_prev))
  *   x_{k+1} = sign(z) max(|z| - lr lambda u, 0)
  *
- * with lr = 1/L, L = max_k (w_k + w_{-k})/2 + mu max(v) ||D||^2 / eps.
+ * with lr = 1/L, L = max_k (w_k + w_{-k})/2 + mu max(v) ||D||^2 / eps + 2 gamma.
  * Reweighting (eq 11) sets u = 1/(|x| + eps1), v = 1/(|Dx| + eps2) from the
  * current map and restarts the momentum.
  *
@@ -64,13 +65,16 @@ typedef struct spg_problem spg_problem;   /* opaque, owned by the library */
 #define SPG_FLAG_COMPENSATED 1   /* iterate stored as fp32 hi + bf16 lo (about 32 significant
                                     bits) with the prox and momentum in fp64; without it the
                                     iterate is plain fp32 and all arithmetic is fp32        */
+#define SPG_FLAG_BF16_STORAGE 2  /* fp32 iterate, but the penalty weights u, v and the
+                                    gradient / extrapolated map are stored in bf16 (fp32
+                                    arithmetic); excludes SPG_FLAG_COMPENSATED             */
 
 typedef struct {
   int32_t nx, ny, nz;   /* grid; each a power of two in [4, 512]                        */
   double lambda;        /* l1 weight (paper alpha), >= 0                                */
   double mu;            /* TV weight (paper beta), >= 0                                 */
   double eps;           /* Nesterov smoothing parameter (paper mu in eq 14), > 0        */
-  double gamma;         /* implicit-descent weight of eq 22; must be 0 in this build    */
+  double gamma;         /* implicit-descent weight of eq 22 (paper gamma), >= 0         */
   int32_t accel;        /* 1: FISTA momentum (default); 0: un-accelerated eq 20-21      */
   int32_t flags;        /* SPG_FLAG_* bits                                              */
 } spg_params;
@@ -114,6 +118,11 @@ spg_status spg_set_penalty_weights(spg_problem* P, const float* d_u, const float
 /* Change lambda and mu (both >= 0).  Recomputes L; resets the momentum. */
 spg_status spg_set_params(spg_problem* P, double lambda, double mu);
 
+/* Implicit-descent term of eq 22: set gamma >= 0 and the previous M-step map x_prev
+ * (nz*ny*nx float, copied into the workspace; NULL = the zero map).  Recomputes L and
+ * resets the momentum. */
+spg_status spg_set_prior(spg_problem* P, double gamma, const float* d_xprev);
+
 /* Set the current map x_0 (nz*ny*nx float) or, with NULL, x_0 = 0.  Resets the momentum. */
 spg_status spg_set_map(spg_problem* P, const float* d_x0);
 
@@ -133,8 +142,9 @@ spg_status spg_get_map(spg_problem* P, float* d_x_out);
 /* Copy the current penalty weights to d_u_out / d_v_out (either may be NULL). */
 spg_status spg_get_penalty_weights(spg_problem* P, float* d_u_out, float* d_v_out);
 
-/* Evaluate, with fp64 accumulation, at the current map x: the smoothed objective
- * F_eps(x) (eq 31 with eq 14), the unsmoothed objective F_0(x) (eq 31), and the
+/* Evaluate, with fp64 accumulation and fp32 transforms in every storage mode, at the
+ * current map x: the smoothed objective F_eps(x) (eq 31 with eq 14, gamma term included),
+ * the unsmoothed objective F_0(x) (eq 31), and the
  * relative fixed-point residual |x - T(x)| / |x| of one un-accelerated step T
  * (eq 20-21), zero exactly at the minimiser.  Any output may be NULL.  Uses one
  * extra forward/inverse FFT pair and synchronises.  SPG_E_DIVERGED if F_eps is

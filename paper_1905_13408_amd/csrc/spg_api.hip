@@ -22,7 +22,7 @@ constexpr int kStatBlocks = 1024;           // grid of the input-check / reweigh
 constexpr int kPartials = 65536;            // fp64 partials in the workspace
 constexpr int kPartA = 0;                   // z-pass objective partials (<= 8192 blocks)
 constexpr int kPartB = 8192;                // kx = 0 / nx/2 plane partials (<= 257 blocks)
-constexpr int kPartC = 16384;               // stencil check partials (5 x <= 8192)
+constexpr int kPartC = 16384;               // stencil check partials (6 x <= 8192)
 constexpr uint64_t kStateMagic = 0x5350475354415431ull;  // "SPGSTAT1"
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -30,7 +30,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
 
 struct Layout {
-  size_t xhi[3], xlo[3], u, v, S, rbuf, ws, wnyq, cs, cnyq, tw_m, tw_n, tw_y, tw_z, part, res, total;
+  size_t xhi[3], xlo[3], u, v, S, rbuf, xprev, ws, w0p, wnyq, cs, c0p, cnyq, tw_m, tw_n, tw_y, tw_z, part, res, total;
 };
 
 Layout make_layout(const spg_params& p) {
@@ -38,6 +38,7 @@ Layout make_layout(const spg_params& p) {
   const size_t nvox = (size_t)p.nx * p.ny * p.nz;
   const size_t P = (size_t)p.nx / 2;
   const bool comp = (p.flags & SPG_FLAG_COMPENSATED) != 0;
+  const size_t rbytes = (p.flags & SPG_FLAG_BF16_STORAGE) ? 2 : 4;  // weights and map buffer
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -46,13 +47,16 @@ Layout make_layout(const spg_params& p) {
   };
   for (int s = 0; s < 3; ++s) L.xhi[s] = take(nvox * 4);
   for (int s = 0; s < 3; ++s) L.xlo[s] = comp ? take(nvox * 2) : 0;
-  L.u = take(nvox * 4);
-  L.v = take(nvox * 4);
+  L.u = take(nvox * rbytes);
+  L.v = take(nvox * rbytes);
   L.S = take((size_t)p.nz * p.ny * P * 8);
-  L.rbuf = take(nvox * 4);
+  L.rbuf = take(nvox * rbytes);
+  L.xprev = take(nvox * 4);
   L.ws = take((size_t)p.nz * p.ny * P * 4);
+  L.w0p = take((size_t)p.nz * p.ny * 4);
   L.wnyq = take((size_t)p.nz * p.ny * 4);
   L.cs = take((size_t)p.nz * p.ny * P * 8);
+  L.c0p = take((size_t)p.nz * p.ny * 8);
   L.cnyq = take((size_t)p.nz * p.ny * 8);
   L.tw_m = take(P * 8);
   L.tw_n = take((size_t)p.nx * 8);
@@ -74,13 +78,22 @@ const char* check_params(const spg_params* p, spg_status* st) {
   if (!std::isfinite(p->eps) || p->eps <= 0) return "eps must be finite and > 0";
   if (!std::isfinite(p->gamma) || p->gamma < 0) return "gamma must be finite and >= 0";
   if (p->accel != 0 && p->accel != 1) return "accel must be 0 or 1";
-  if (p->flags & ~SPG_FLAG_COMPENSATED) return "unknown flag bits";
-  if (p->gamma != 0) {
-    *st = SPG_E_UNSUPPORTED;
-    return "gamma != 0 (implicit-descent term) is not implemented in this build";
-  }
+  if (p->flags & ~(SPG_FLAG_COMPENSATED | SPG_FLAG_BF16_STORAGE)) return "unknown flag bits";
+  if ((p->flags & SPG_FLAG_COMPENSATED) && (p->flags & SPG_FLAG_BF16_STORAGE))
+    return "SPG_FLAG_COMPENSATED and SPG_FLAG_BF16_STORAGE are exclusive";
   *st = SPG_OK;
   return nullptr;
+}
+
+// Round to the nearest bf16 (ties to even), as the device conversion does.
+double bf16_round(double v) {
+  float f = (float)v;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  u &= 0xFFFF0000u;
+  std::memcpy(&f, &u, 4);
+  return f;
 }
 
 double dnorm2_of(int nx, int ny, int nz) {
@@ -108,6 +121,8 @@ struct spg_problem {
   Layout lay{};
   Dims d{};
   bool comp = false;
+  int store = ST_PLAIN;
+  bool prior_set = false;
   bool data_set = false;
   bool primed = false;
   bool sticky = false;
@@ -134,8 +149,10 @@ struct spg_problem {
   float* rbuf() { return at<float>(lay.rbuf); }
   double* part() { return at<double>(lay.part); }
   double* res() { return at<double>(lay.res); }
-  const float* uptr() { return unif_u ? nullptr : at<float>(lay.u); }
-  const float* vptr() { return unif_v ? nullptr : at<float>(lay.v); }
+  bool bf() const { return store == ST_BF16; }
+  const void* uptr() { return unif_u ? nullptr : at<void>(lay.u); }
+  const void* vptr() { return unif_v ? nullptr : at<void>(lay.v); }
+  size_t wbytes() const { return (size_t)d.nvox * (store == ST_BF16 ? 2 : 4); }
 };
 
 namespace {
@@ -199,7 +216,7 @@ spg_status read_results(spg_problem* P, double* host, int n) {
 // Forward FFT of the x-axis rows of rbuf (already holding y) followed by the y, z
 // passes with the weight step, the y inverse and the x inverse into rbuf.  obj: also
 // collect the data-term partials.
-spg_status gradient_pipeline(spg_problem* P, bool obj, int* nA, int* nB) {
+spg_status gradient_pipeline(spg_problem* P, bool obj, int* nA, int* nB, void* gout, bool gout_bf16) {
   const Dims& d = P->d;
   hipStream_t st = P->stream;
   const float2* twy = P->at<float2>(P->lay.tw_y);
@@ -213,21 +230,22 @@ spg_status gradient_pipeline(spg_problem* P, bool obj, int* nA, int* nB) {
   SPG_CK(P, launch_fft_cols(d, P->S(), 2, obj ? 3 : 2, twz, wsp, csp, obj ? P->part() + kPartA : nullptr, st, nA));
   prof_end(P, SPG_KERNEL_FFT_Z_WEIGHT);
   prof_begin(P, SPG_KERNEL_DC_NYQUIST);
-  SPG_CK(P, launch_dc_nyquist(d, P->S(), twz, wsp, P->at<float>(P->lay.wnyq), csp, P->at<float2>(P->lay.cnyq),
+  SPG_CK(P, launch_dc_nyquist(d, P->S(), twz, P->at<float>(P->lay.w0p), P->at<float>(P->lay.wnyq),
+                              P->at<float2>(P->lay.c0p), P->at<float2>(P->lay.cnyq),
                               obj ? P->part() + kPartB : nullptr, st, nB));
   prof_end(P, SPG_KERNEL_DC_NYQUIST);
   prof_begin(P, SPG_KERNEL_FFT_Y_INV);
   SPG_CK(P, launch_fft_cols(d, P->S(), 1, 1, twy, nullptr, nullptr, nullptr, st, nullptr));
   prof_end(P, SPG_KERNEL_FFT_Y_INV);
   prof_begin(P, SPG_KERNEL_C2R_X);
-  SPG_CK(P, launch_c2r_x(d, P->S(), P->rbuf(), P->at<float2>(P->lay.tw_m), P->at<float2>(P->lay.tw_n), st));
+  SPG_CK(P, launch_c2r_x(d, P->S(), gout, gout_bf16, P->at<float2>(P->lay.tw_m), P->at<float2>(P->lay.tw_n), st));
   prof_end(P, SPG_KERNEL_C2R_X);
   return SPG_OK;
 }
 
-spg_status r2c(spg_problem* P) {
+spg_status r2c(spg_problem* P, const void* rin, bool rin_bf16) {
   prof_begin(P, SPG_KERNEL_R2C_X);
-  SPG_CK(P, launch_r2c_x(P->d, P->rbuf(), P->S(), P->at<float2>(P->lay.tw_m), P->at<float2>(P->lay.tw_n),
+  SPG_CK(P, launch_r2c_x(P->d, rin, rin_bf16, P->S(), P->at<float2>(P->lay.tw_m), P->at<float2>(P->lay.tw_n),
                          P->stream));
   prof_end(P, SPG_KERNEL_R2C_X);
   return SPG_OK;
@@ -244,6 +262,9 @@ ProxArgs prox_args(spg_problem* P, int nxt, double m, double m_next) {
   a.xn_lo = P->xlo(nxt);
   a.u = P->uptr();
   a.v = P->vptr();
+  a.gin = nullptr;
+  a.xprev = (P->prm.gamma != 0 && P->prior_set) ? P->at<float>(P->lay.xprev) : nullptr;
+  a.gamma = P->prm.gamma;
   a.partials = nullptr;
   a.nx = P->d.nx;
   a.ny = P->d.ny;
@@ -307,6 +328,7 @@ spg_status spg_create(const spg_params* p, void* d_workspace, size_t bytes, void
   P->d.P = p->nx / 2;
   P->d.nvox = (long long)p->nx * p->ny * p->nz;
   P->comp = (p->flags & SPG_FLAG_COMPENSATED) != 0;
+  P->store = P->comp ? ST_COMP : ((p->flags & SPG_FLAG_BF16_STORAGE) ? ST_BF16 : ST_PLAIN);
   P->dn2 = dnorm2_of(p->nx, p->ny, p->nz);
 
   // Twiddle tables exp(-2 pi i m / n), computed in fp64 and rounded once.
@@ -359,8 +381,9 @@ spg_status spg_set_data(spg_problem* P, const float* d_w, const float* d_b) {
   if (r[0] > 0) return set_err(P, SPG_E_NONFINITE, "w or b holds NaN/Inf values");
   if (r[1] < 0) return set_err(P, SPG_E_INVAL, "negative Fourier weight");
   // 2. fold onto the packed half spectrum
-  SPG_CK(P, launch_fold(d, d_w, b, P->at<float>(P->lay.ws), P->at<float>(P->lay.wnyq), P->at<float2>(P->lay.cs),
-                        P->at<float2>(P->lay.cnyq), part, kStatBlocks, P->stream));
+  SPG_CK(P, launch_fold(d, d_w, b, P->at<float>(P->lay.ws), P->at<float>(P->lay.w0p), P->at<float>(P->lay.wnyq),
+                        P->at<float2>(P->lay.cs), P->at<float2>(P->lay.c0p), P->at<float2>(P->lay.cnyq), part,
+                        kStatBlocks, P->stream));
   const int ops1[1] = {RED_OP_MAX};
   SPG_CK(P, launch_reduce(part, kStatBlocks, 1, ops1, P->res(), P->stream));
   double mx;
@@ -391,8 +414,13 @@ spg_status spg_set_penalty_weights(spg_problem* P, const float* d_u, const float
     if (k == 1) vmax = r[2];
   }
   const size_t bytes = (size_t)P->d.nvox * 4;
-  if (d_u) SPG_CK(P, hipMemcpyAsync(P->at<float>(P->lay.u), d_u, bytes, hipMemcpyDeviceToDevice, P->stream));
-  if (d_v) SPG_CK(P, hipMemcpyAsync(P->at<float>(P->lay.v), d_v, bytes, hipMemcpyDeviceToDevice, P->stream));
+  void* dst[2] = {P->at<void>(P->lay.u), P->at<void>(P->lay.v)};
+  for (int k = 0; k < 2; ++k) {
+    if (!arr[k]) continue;
+    if (P->bf()) SPG_CK(P, launch_f32_to_bf16(arr[k], reinterpret_cast<uint16_t*>(dst[k]), P->d.nvox, P->stream));
+    else SPG_CK(P, hipMemcpyAsync(dst[k], arr[k], bytes, hipMemcpyDeviceToDevice, P->stream));
+  }
+  if (P->bf() && d_v) vmax = bf16_round(vmax);  // rounding is monotonic: max of the stored values
   P->unif_u = d_u == nullptr;
   P->unif_v = d_v == nullptr;
   P->vmax = vmax;
@@ -408,6 +436,20 @@ spg_status spg_set_params(spg_problem* P, double lambda, double mu) {
     return set_err(P, SPG_E_INVAL, "lambda and mu must be finite and >= 0");
   P->prm.lambda = lambda;
   P->prm.mu = mu;
+  recompute_L(P);
+  restart(P);
+  return SPG_OK;
+}
+
+spg_status spg_set_prior(spg_problem* P, double gamma, const float* d_xprev) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if (!std::isfinite(gamma) || gamma < 0) return set_err(P, SPG_E_INVAL, "gamma must be finite and >= 0");
+  if (d_xprev)
+    SPG_CK(P, hipMemcpyAsync(P->at<float>(P->lay.xprev), d_xprev, (size_t)P->d.nvox * 4, hipMemcpyDeviceToDevice,
+                             P->stream));
+  P->prior_set = d_xprev != nullptr;
+  P->prm.gamma = gamma;
   recompute_L(P);
   restart(P);
   return SPG_OK;
@@ -431,19 +473,19 @@ spg_status spg_run(spg_problem* P, int32_t K, spg_stats* stats) {
   for (int it = 0; it < K; ++it) {
     if (!P->primed) {
       SPG_CK(P, launch_prime(d, P->rbuf(), P->xhi(P->cur), P->xlo(P->cur), P->xhi(P->old), P->xlo(P->old),
-                             P->m_cur, P->m_cur != 0.0, P->comp, P->stream));
-      if ((s = r2c(P))) return s;
+                             P->m_cur, P->m_cur != 0.0, P->store, P->stream));
+      if ((s = r2c(P, P->rbuf(), P->bf()))) return s;
       P->primed = true;
     }
-    if ((s = gradient_pipeline(P, false, nullptr, nullptr))) return s;
+    if ((s = gradient_pipeline(P, false, nullptr, nullptr, P->rbuf(), P->bf()))) return s;
     const double t_next = P->prm.accel ? 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * P->t * P->t)) : 1.0;
     const double m_next = P->prm.accel ? (P->t - 1.0) / t_next : 0.0;
     const int nxt = 3 - P->cur - P->old;
     ProxArgs a = prox_args(P, nxt, P->m_cur, m_next);
     prof_begin(P, SPG_KERNEL_PROX_TV);
-    SPG_CK(P, launch_prox_tv(d, a, P->comp, false, P->stream));
+    SPG_CK(P, launch_prox_tv(d, a, P->store, false, P->stream));
     prof_end(P, SPG_KERNEL_PROX_TV);
-    if ((s = r2c(P))) return s;
+    if ((s = r2c(P, P->rbuf(), P->bf()))) return s;
     P->old = P->cur;
     P->cur = nxt;
     P->t = t_next;
@@ -466,8 +508,8 @@ spg_status spg_reweight(spg_problem* P, double eps1, double eps2) {
   if (s) return s;
   if (!std::isfinite(eps1) || !std::isfinite(eps2) || eps1 <= 0 || eps2 <= 0)
     return set_err(P, SPG_E_INVAL, "eps1 and eps2 must be finite and > 0");
-  SPG_CK(P, launch_reweight(P->d, P->xhi(P->cur), P->xlo(P->cur), P->at<float>(P->lay.u), P->at<float>(P->lay.v),
-                            eps1, eps2, P->comp, P->part(), kStatBlocks, P->stream));
+  SPG_CK(P, launch_reweight(P->d, P->xhi(P->cur), P->xlo(P->cur), P->at<void>(P->lay.u), P->at<void>(P->lay.v),
+                            eps1, eps2, P->store, P->part(), kStatBlocks, P->stream));
   const int ops[1] = {RED_OP_MAX};
   SPG_CK(P, launch_reduce(P->part(), kStatBlocks, 1, ops, P->res(), P->stream));
   double vmax;
@@ -493,13 +535,14 @@ spg_status spg_get_penalty_weights(spg_problem* P, float* d_u_out, float* d_v_ou
   spg_status s = usable(P);
   if (s) return s;
   const size_t bytes = (size_t)P->d.nvox * 4;
-  if (d_u_out) {
-    if (P->unif_u) SPG_CK(P, launch_fill(d_u_out, P->d.nvox, 1.0f, P->stream));
-    else SPG_CK(P, hipMemcpyAsync(d_u_out, P->at<float>(P->lay.u), bytes, hipMemcpyDeviceToDevice, P->stream));
-  }
-  if (d_v_out) {
-    if (P->unif_v) SPG_CK(P, launch_fill(d_v_out, P->d.nvox, 1.0f, P->stream));
-    else SPG_CK(P, hipMemcpyAsync(d_v_out, P->at<float>(P->lay.v), bytes, hipMemcpyDeviceToDevice, P->stream));
+  float* outs[2] = {d_u_out, d_v_out};
+  const bool unif[2] = {P->unif_u, P->unif_v};
+  const size_t offs[2] = {P->lay.u, P->lay.v};
+  for (int k = 0; k < 2; ++k) {
+    if (!outs[k]) continue;
+    if (unif[k]) SPG_CK(P, launch_fill(outs[k], P->d.nvox, 1.0f, P->stream));
+    else if (P->bf()) SPG_CK(P, launch_bf16_to_f32(P->at<uint16_t>(offs[k]), outs[k], P->d.nvox, P->stream));
+    else SPG_CK(P, hipMemcpyAsync(outs[k], P->at<float>(offs[k]), bytes, hipMemcpyDeviceToDevice, P->stream));
   }
   return SPG_OK;
 }
@@ -509,26 +552,32 @@ spg_status spg_final_check(spg_problem* P, double* F_eps, double* F_0, double* k
   if (s) return s;
   if (!P->data_set) return set_err(P, SPG_E_STATE, "spg_set_data has not succeeded");
   const Dims& d = P->d;
-  SPG_CK(P, launch_prime(d, P->rbuf(), P->xhi(P->cur), P->xlo(P->cur), nullptr, nullptr, 0.0, 0, P->comp, P->stream));
+  // The check runs in fp32 in every storage mode: the forward transform reads the fp32 (hi)
+  // words of x, and the data gradient goes to the spare ring slot as fp32.
+  const int spare = 3 - P->cur - P->old;
   P->primed = false;
-  if ((s = r2c(P))) return s;
+  if ((s = r2c(P, P->xhi(P->cur), false))) return s;
   int nA = 0, nB = 0;
-  if ((s = gradient_pipeline(P, true, &nA, &nB))) return s;
+  if ((s = gradient_pipeline(P, true, &nA, &nB, P->xhi(spare), false))) return s;
   ProxArgs a = prox_args(P, P->cur, 0.0, 0.0);
   a.read_old = 0;
+  a.gin = P->xhi(spare);
   const int nC = prox_num_blocks(d);
   a.partials = P->part() + kPartC;
-  SPG_CK(P, launch_prox_tv(d, a, P->comp, true, P->stream));
+  prof_begin(P, SPG_KERNEL_PROX_TV);
+  SPG_CK(P, launch_prox_tv(d, a, P->store, true, P->stream));
+  prof_end(P, SPG_KERNEL_PROX_TV);
   const int sum1[1] = {RED_OP_SUM};
-  const int sum5[5] = {RED_OP_SUM, RED_OP_SUM, RED_OP_SUM, RED_OP_SUM, RED_OP_SUM};
+  const int sum6[6] = {RED_OP_SUM, RED_OP_SUM, RED_OP_SUM, RED_OP_SUM, RED_OP_SUM, RED_OP_SUM};
   SPG_CK(P, launch_reduce(P->part() + kPartA, nA, 1, sum1, P->res() + 0, P->stream));
   SPG_CK(P, launch_reduce(P->part() + kPartB, nB, 1, sum1, P->res() + 1, P->stream));
-  SPG_CK(P, launch_reduce(P->part() + kPartC, nC, 5, sum5, P->res() + 2, P->stream));
-  double r[7];
-  if ((s = read_results(P, r, 7))) return s;
+  SPG_CK(P, launch_reduce(P->part() + kPartC, nC, 6, sum6, P->res() + 2, P->stream));
+  double r[8];
+  if ((s = read_results(P, r, 8))) return s;
   const double data = P->C0 + r[0] + r[1];
-  const double fe = data + P->prm.lambda * r[2] + P->prm.mu * r[3];
-  const double f0 = data + P->prm.lambda * r[2] + P->prm.mu * r[4];
+  const double prior = P->prm.gamma * r[7];
+  const double fe = data + P->prm.lambda * r[2] + P->prm.mu * r[3] + prior;
+  const double f0 = data + P->prm.lambda * r[2] + P->prm.mu * r[4] + prior;
   const double kkt = std::sqrt(r[5]) / (r[6] > 0 ? std::sqrt(r[6]) : 1.0);
   if (F_eps) *F_eps = fe;
   if (F_0) *F_0 = f0;
@@ -544,13 +593,13 @@ struct StateHeader {
   int32_t nx, ny, nz, flags;
   int32_t unif_u, unif_v, j, round;
   int64_t iters_done;
-  double t, m_cur, vmax, lambda, mu, eps;
+  double t, m_cur, vmax, lambda, mu, eps, gamma;
 };
 
 static size_t state_bytes(const spg_problem* P) {
   const size_t nvox = (size_t)P->d.nvox;
   const size_t slot = align_up(nvox * 4) + (P->comp ? align_up(nvox * 2) : 0);
-  return kAlign + 2 * slot + 2 * align_up(nvox * 4);
+  return kAlign + 2 * slot + 2 * align_up(P->wbytes());
 }
 
 spg_status spg_state_size(const spg_problem* P, size_t* bytes) {
@@ -569,7 +618,7 @@ spg_status spg_get_state(spg_problem* P, void* d_buf, size_t bytes) {
   h.unif_u = P->unif_u; h.unif_v = P->unif_v; h.j = P->j; h.round = P->round;
   h.iters_done = P->iters_done;
   h.t = P->t; h.m_cur = P->m_cur; h.vmax = P->vmax;
-  h.lambda = P->prm.lambda; h.mu = P->prm.mu; h.eps = P->prm.eps;
+  h.lambda = P->prm.lambda; h.mu = P->prm.mu; h.eps = P->prm.eps; h.gamma = P->prm.gamma;
   char* dst = reinterpret_cast<char*>(d_buf);
   const size_t nvox = (size_t)P->d.nvox;
   size_t off = kAlign;
@@ -582,9 +631,10 @@ spg_status spg_get_state(spg_problem* P, void* d_buf, size_t bytes) {
       off += align_up(nvox * 2);
     }
   }
-  if (!P->unif_u) SPG_CK(P, hipMemcpyAsync(dst + off, P->at<float>(P->lay.u), nvox * 4, hipMemcpyDeviceToDevice, P->stream));
-  off += align_up(nvox * 4);
-  if (!P->unif_v) SPG_CK(P, hipMemcpyAsync(dst + off, P->at<float>(P->lay.v), nvox * 4, hipMemcpyDeviceToDevice, P->stream));
+  const size_t wb = P->wbytes();
+  if (!P->unif_u) SPG_CK(P, hipMemcpyAsync(dst + off, P->at<void>(P->lay.u), wb, hipMemcpyDeviceToDevice, P->stream));
+  off += align_up(wb);
+  if (!P->unif_v) SPG_CK(P, hipMemcpyAsync(dst + off, P->at<void>(P->lay.v), wb, hipMemcpyDeviceToDevice, P->stream));
   SPG_CK(P, hipMemcpyAsync(dst, &h, sizeof(h), hipMemcpyHostToDevice, P->stream));
   SPG_CK(P, hipStreamSynchronize(P->stream));
   return SPG_OK;
@@ -611,9 +661,10 @@ spg_status spg_set_state(spg_problem* P, const void* d_buf, size_t bytes) {
       off += align_up(nvox * 2);
     }
   }
-  if (!h.unif_u) SPG_CK(P, hipMemcpyAsync(P->at<float>(P->lay.u), src + off, nvox * 4, hipMemcpyDeviceToDevice, P->stream));
-  off += align_up(nvox * 4);
-  if (!h.unif_v) SPG_CK(P, hipMemcpyAsync(P->at<float>(P->lay.v), src + off, nvox * 4, hipMemcpyDeviceToDevice, P->stream));
+  const size_t wb = P->wbytes();
+  if (!h.unif_u) SPG_CK(P, hipMemcpyAsync(P->at<void>(P->lay.u), src + off, wb, hipMemcpyDeviceToDevice, P->stream));
+  off += align_up(wb);
+  if (!h.unif_v) SPG_CK(P, hipMemcpyAsync(P->at<void>(P->lay.v), src + off, wb, hipMemcpyDeviceToDevice, P->stream));
   P->cur = 0;
   P->old = 1;
   P->unif_u = h.unif_u != 0;
@@ -627,6 +678,7 @@ spg_status spg_set_state(spg_problem* P, const void* d_buf, size_t bytes) {
   P->prm.lambda = h.lambda;
   P->prm.mu = h.mu;
   P->prm.eps = h.eps;
+  P->prm.gamma = h.gamma;
   P->primed = false;
   recompute_L(P);
   return SPG_OK;

@@ -25,22 +25,30 @@ constexpr int PT_ZC = 32;
 // Reductions: per-block fp64 partials, summed in fixed order by k_reduce.
 constexpr int RED_OP_SUM = 0, RED_OP_MAX = 1, RED_OP_MIN = 2;
 
+// Storage modes: plain fp32 iterate; compensated fp32 hi + bf16 lo iterate with fp64
+// prox arithmetic; fp32 iterate with the penalty weights and the gradient / extrapolated
+// map stored in bf16.
+constexpr int ST_PLAIN = 0, ST_COMP = 1, ST_BF16 = 2;
+
 // Arguments of the fused stencil / prox kernel.
 struct ProxArgs {
-  float* rbuf;                  // in: data gradient of y_k (real map); out: y_{k+1}
+  void* rbuf;                   // in: data gradient of y_k (real map); out: y_{k+1}
+                                // (fp32, bf16 in ST_BF16)
+  const float* gin;             // check mode: fp32 data gradient of x_k
   const float* xk_hi;           // x_k  (fp32 hi part)
   const uint16_t* xk_lo;        // x_k  (bf16 lo part; compensated mode only)
   const float* xo_hi;           // x_{k-1}
   const uint16_t* xo_lo;
   float* xn_hi;                 // x_{k+1}
   uint16_t* xn_lo;
-  const float* u;               // l1 weights or nullptr (uniform 1)
-  const float* v;               // TV weights or nullptr (uniform 1)
+  const void* u;                // l1 weights or nullptr (uniform 1); fp32, bf16 in ST_BF16
+  const void* v;                // TV weights or nullptr (uniform 1); fp32, bf16 in ST_BF16
+  const float* xprev;           // previous M-step map of the gamma term, nullptr = 0
   double* partials;             // check mode: 5 x nblocks fp64 partials
   int nx, ny, nz;
   int read_old;                 // 0 when m == 0: x_{k-1} is not read
   double m, m_next;             // momentum for y_k and for y_{k+1}
-  double lr, lam, mu;
+  double lr, lam, mu, gamma;
   float eps;
 };
 
@@ -49,29 +57,31 @@ int prox_num_blocks(const Dims& d);
 hipError_t launch_fft_cols(const Dims& d, float2* S, int axis /*1 = y, 2 = z*/, int mode,
                            const float2* tw, const float* ws, const float2* cs, double* partials,
                            hipStream_t st, int* nblocks_out);
-hipError_t launch_dc_nyquist(const Dims& d, float2* S, const float2* tw_z, const float* ws,
-                             const float* wnyq, const float2* cs, const float2* cnyq, double* partials,
+hipError_t launch_dc_nyquist(const Dims& d, float2* S, const float2* tw_z, const float* w0p,
+                             const float* wnyq, const float2* c0p, const float2* cnyq, double* partials,
                              hipStream_t st, int* nblocks_out);
-hipError_t launch_r2c_x(const Dims& d, const float* rin, float2* S, const float2* tw_m,
+hipError_t launch_r2c_x(const Dims& d, const void* rin, bool rin_bf16, float2* S, const float2* tw_m,
                         const float2* tw_n, hipStream_t st);
-hipError_t launch_c2r_x(const Dims& d, const float2* S, float* rout, const float2* tw_m,
+hipError_t launch_c2r_x(const Dims& d, const float2* S, void* rout, bool rout_bf16, const float2* tw_m,
                         const float2* tw_n, hipStream_t st);
-hipError_t launch_prox_tv(const Dims& d, const ProxArgs& a, bool compensated, bool check, hipStream_t st);
+hipError_t launch_prox_tv(const Dims& d, const ProxArgs& a, int store, bool check, hipStream_t st);
 
-hipError_t launch_prime(const Dims& d, float* rbuf, const float* xk_hi, const uint16_t* xk_lo,
+hipError_t launch_prime(const Dims& d, void* rbuf, const float* xk_hi, const uint16_t* xk_lo,
                         const float* xo_hi, const uint16_t* xo_lo, double m, int read_old,
-                        bool compensated, hipStream_t st);
+                        int store, hipStream_t st);
 hipError_t launch_set_map(const Dims& d, const float* x0, float* hi, uint16_t* lo, hipStream_t st);
 hipError_t launch_get_map(const Dims& d, const float* hi, const uint16_t* lo, float* out, bool compensated,
                           hipStream_t st);
-hipError_t launch_fold(const Dims& d, const float* w, const float2* b, float* ws, float* wnyq, float2* cs,
-                       float2* cnyq, double* partials, int nblocks, hipStream_t st);
+hipError_t launch_fold(const Dims& d, const float* w, const float2* b, float* ws, float* w0p, float* wnyq,
+                       float2* cs, float2* c0p, float2* cnyq, double* partials, int nblocks, hipStream_t st);
 hipError_t launch_data_stats(const Dims& d, const float* w, const float2* b, double* partials, int nblocks,
                              hipStream_t st);
 hipError_t launch_weight_stats(const Dims& d, const float* a, double* partials, int nblocks, hipStream_t st);
-hipError_t launch_reweight(const Dims& d, const float* hi, const uint16_t* lo, float* u, float* v,
-                           double eps1, double eps2, bool compensated, double* partials, int nblocks,
+hipError_t launch_reweight(const Dims& d, const float* hi, const uint16_t* lo, void* u, void* v,
+                           double eps1, double eps2, int store, double* partials, int nblocks,
                            hipStream_t st);
+hipError_t launch_f32_to_bf16(const float* src, uint16_t* dst, long long n, hipStream_t st);
+hipError_t launch_bf16_to_f32(const uint16_t* src, float* dst, long long n, hipStream_t st);
 hipError_t launch_fill(float* dst, long long n, float value, hipStream_t st);
 hipError_t launch_reduce(const double* partials, int n, int nq, const int* ops, double* out, hipStream_t st);
 

@@ -40,6 +40,18 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
+// Element i of a real array stored as fp32 or (BF) bf16.
+template <bool BF>
+__device__ __forceinline__ float ld_real(const void* p, long long i) {
+  if constexpr (BF) return bf16_to_f32(reinterpret_cast<const uint16_t*>(p)[i]);
+  else return reinterpret_cast<const float*>(p)[i];
+}
+template <bool BF>
+__device__ __forceinline__ void st_real(void* p, long long i, float v) {
+  if constexpr (BF) reinterpret_cast<uint16_t*>(p)[i] = f32_to_bf16(v);
+  else reinterpret_cast<float*>(p)[i] = v;
+}
+
 // ---------------------------------------------------------------- radix butterflies
 // Forward transforms use exp(-2 pi i / R), inverse ones exp(+2 pi i / R); no scaling.
 
@@ -274,6 +286,18 @@ struct ColT {
   static constexpr int T = L >= 256 ? 32 : FftPlan<L>::T;
 };
 
+// ---------------------------------------------------------------- XCD-aware block order
+// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each with its
+// own L2.  Remapping hardware block b to logical tile (b % 8) * (n / 8) + b / 8 gives
+// every XCD a contiguous run of logical tiles, so neighbouring tiles that share cache
+// lines (stencil halos, the two 64-byte halves of a 128-byte row segment) meet in the
+// same L2.  The last n % 8 blocks keep their index.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int q = n >> 3;
+  if (b >= (q << 3)) return b;
+  return (b & 7) * q + (b >> 3);
+}
+
 // ---------------------------------------------------------------- block reductions (fp64)
 
 template <int OP>
@@ -319,8 +343,9 @@ __global__ void __launch_bounds__(512) k_fft_cols(float2* __restrict__ S, int P,
   constexpr int E = RegPlan<L, T>::E;
   const int tid = threadIdx.x;
   const int c = tid % NT, q = tid / NT;
-  const int tile = blockIdx.x % ntiles;
-  const int batch = blockIdx.x / ntiles;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = blk % ntiles;
+  const int batch = blk / ntiles;
   const int kx = tile * NT + c;
   const bool valid = kx < P;
   // block-uniform base pointers and 32-bit per-lane element offsets (every offset of a
@@ -377,7 +402,7 @@ __global__ void __launch_bounds__(512) k_fft_cols(float2* __restrict__ S, int P,
     }
     if constexpr (MODE == 3) {
       double r = block_reduce<RED_OP_SUM>(acc, s_red);
-      if (tid == 0) partials[blockIdx.x] = r;
+      if (tid == 0) partials[blk] = r;
     }
     __syncthreads();  // the forward transform's last stage read the LDS planes
     fft_reg<L, true, T>(a, re, im, NT, q, s_tw);
@@ -390,14 +415,15 @@ __global__ void __launch_bounds__(512) k_fft_cols(float2* __restrict__ S, int P,
 
 // ---------------------------------------------------------------- packed kx = 0 / nx/2 plane
 // The packed slot holds Z = X0 + i XN where X0 and XN are the (complex) yz spectra of
-// the real x-axis planes kx = 0 and kx = nx/2.  Both are Hermitian in (ky, kz), so
+// the real x-axis planes kx = 0 and kx = nx/2.  Their folded weights and data terms are
+// stored as separate planes in [ky][kz] order so that a block reads contiguous runs.  Both are Hermitian in (ky, kz), so
 // X0(k) = (Z(k) + conj Z(-k))/2 and XN(k) = (Z(k) - conj Z(-k))/(2i).  One block
 // handles the column pair ky, -ky so that every partner is on chip.
 
 template <int L, bool OBJ>
 __global__ void __launch_bounds__(256) k_dc_nyquist(float2* __restrict__ S, int P, int ny,
-                                                    const float2* __restrict__ tw, const float* __restrict__ ws,
-                                                    const float* __restrict__ wnyq, const float2* __restrict__ cs,
+                                                    const float2* __restrict__ tw, const float* __restrict__ w0p,
+                                                    const float* __restrict__ wnyq, const float2* __restrict__ c0p,
                                                     const float2* __restrict__ cnyq, double* __restrict__ partials) {
   __shared__ float s_re[L * 2];
   __shared__ float s_im[L * 2];
@@ -434,10 +460,9 @@ __global__ void __launch_bounds__(256) k_dc_nyquist(float2* __restrict__ S, int 
       const float2 A = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
       const float2 dd = make_float2(0.5f * (z1.x - z2.x), 0.5f * (z1.y + z2.y));
       const float2 B = make_float2(dd.y, -dd.x);
-      const long long off = (long long)kz * pstride + base;
-      const long long offn = (long long)kz * ny + myky;
-      const float w0 = ws[off], wn = wnyq[offn];
-      const float2 c0 = cs[off], cn = cnyq[offn];
+      const long long offn = (long long)myky * L + kz;
+      const float w0 = w0p[offn], wn = wnyq[offn];
+      const float2 c0 = c0p[offn], cn = cnyq[offn];
       if constexpr (OBJ) {
         if (c == 0 || ky != kyp)
           acc += 0.5 * (double)w0 * ((double)A.x * A.x + (double)A.y * A.y) - ((double)c0.x * A.x + (double)c0.y * A.y) +
@@ -474,8 +499,8 @@ __global__ void __launch_bounds__(256) k_dc_nyquist(float2* __restrict__ S, int 
 // the unnormalised inverse of the Hermitian row spectrum.
 // Block: NR rows; thread (row c = tid / T, q = tid % T); LDS row pitch M + 1.
 
-template <int M>
-__global__ void __launch_bounds__(256) k_r2c_x(const float* __restrict__ rin, float2* __restrict__ S, int nrows,
+template <int M, bool BF>
+__global__ void __launch_bounds__(256) k_r2c_x(const void* __restrict__ rin, float2* __restrict__ S, int nrows,
                                                const float2* __restrict__ twm, const float2* __restrict__ twn,
                                                int NR) {
   __shared__ float s_re[(M + 1) * 16];
@@ -487,10 +512,19 @@ __global__ void __launch_bounds__(256) k_r2c_x(const float* __restrict__ rin, fl
   const int c = tid / T, q = tid % T;
   const int row = blockIdx.x * NR + c;
   const bool valid = row < nrows;
-  const float2* src = reinterpret_cast<const float2*>(rin) + (long long)row * M;
   float2 a[E];
+  if constexpr (BF) {  // two bf16 samples per 32-bit word, even sample in the low half
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(rin) + (long long)row * M;
 #pragma unroll
-  for (int i = 0; i < E; ++i) a[i] = valid ? src[q + T * i] : make_float2(0.f, 0.f);
+    for (int i = 0; i < E; ++i) {
+      const uint32_t wd = valid ? src[q + T * i] : 0u;
+      a[i] = make_float2(bf16_to_f32((uint16_t)(wd & 0xFFFFu)), bf16_to_f32((uint16_t)(wd >> 16)));
+    }
+  } else {
+    const float2* src = reinterpret_cast<const float2*>(rin) + (long long)row * M;
+#pragma unroll
+    for (int i = 0; i < E; ++i) a[i] = valid ? src[q + T * i] : make_float2(0.f, 0.f);
+  }
   for (int i = tid; i < M; i += blockDim.x) s_tw[i] = twm[i];
   __syncthreads();
   float* re = s_re + c * (M + 1);
@@ -524,8 +558,8 @@ __global__ void __launch_bounds__(256) k_r2c_x(const float* __restrict__ rin, fl
   }
 }
 
-template <int M>
-__global__ void __launch_bounds__(256) k_c2r_x(const float2* __restrict__ S, float* __restrict__ rout, int nrows,
+template <int M, bool BF>
+__global__ void __launch_bounds__(256) k_c2r_x(const float2* __restrict__ S, void* __restrict__ rout, int nrows,
                                                const float2* __restrict__ twm, const float2* __restrict__ twn,
                                                int NR) {
   __shared__ float s_re[(M + 1) * 16];
@@ -572,9 +606,16 @@ __global__ void __launch_bounds__(256) k_c2r_x(const float2* __restrict__ S, flo
   __syncthreads();
   fft_reg<M, true>(a, re, im, 1, q, s_tw);
   if (valid) {
-    float2* dst = reinterpret_cast<float2*>(rout) + (long long)row * M;
+    if constexpr (BF) {
+      uint32_t* dst = reinterpret_cast<uint32_t*>(rout) + (long long)row * M;
 #pragma unroll
-    for (int i = 0; i < E; ++i) dst[q + T * i] = a[i];
+      for (int i = 0; i < E; ++i)
+        dst[q + T * i] = (uint32_t)f32_to_bf16(a[i].x) | ((uint32_t)f32_to_bf16(a[i].y) << 16);
+    } else {
+      float2* dst = reinterpret_cast<float2*>(rout) + (long long)row * M;
+#pragma unroll
+      for (int i = 0; i < E; ++i) dst[q + T * i] = a[i];
+    }
   }
 }
 
@@ -633,8 +674,10 @@ __device__ __forceinline__ void eval_raw(const ProxArgs& a, const RawX& r, doubl
   }
 }
 
-template <bool COMP, bool CHECK>
+template <int ST, bool CHECK>
 __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
+  constexpr bool COMP = ST == ST_COMP;
+  constexpr bool BF = ST == ST_BF16;
   constexpr int TX = PT_TX, TY = PT_TY;
   constexpr int YW = TX + 2, YH = TY + 2;  // y plane with halo
   constexpr int PW = TX + 1, PH = TY + 1;  // p plane with the +1 shell
@@ -646,9 +689,10 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
 
   const int tid = threadIdx.x;
   const int tx = tid & 63, ty = tid >> 6;  // owns (tx, ty) and (tx, ty + 4)
-  const int bx = blockIdx.x % ntx;
-  const int by = (blockIdx.x / ntx) % nty;
-  const int bz = blockIdx.x / (ntx * nty);
+  const int blk = blockIdx.x;
+  const int bx = blk % ntx;
+  const int by = (blk / ntx) % nty;
+  const int bz = blk / (ntx * nty);
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int x0 = bx * TX, y0 = by * TY;
   const int z0 = bz * PT_ZC;
@@ -692,14 +736,18 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
     for (int h = 0; h < 2; ++h) fetch_raw<COMP>(a, pz + own_off[h], own[h]);
     if (has_halo) fetch_raw<COMP>(a, pz + halo_off, halo);
 #pragma unroll
-    for (int t = 0; t < NPP; ++t) vv[t] = (a.v && p_ok[t]) ? a.v[pz + p_off[t]] : 1.0f;
+    for (int t = 0; t < NPP; ++t) vv[t] = (a.v && p_ok[t]) ? ld_real<BF>(a.v, pz + p_off[t]) : 1.0f;
   };
-  auto fetch_out = [&](int zz, float* g, float* uu) {
+  // inputs of the outputs of plane zz: data gradient, l1 weight and (gamma term) prior map
+  auto fetch_out = [&](int zz, float* g, float* uu, float* xp) {
     const long long pz = (long long)zz * plane;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      g[h] = vown[h] ? a.rbuf[pz + own_off[h]] : 0.f;
-      uu[h] = (a.u && vown[h]) ? a.u[pz + own_off[h]] : 1.0f;
+      const long long i = pz + own_off[h];
+      if constexpr (CHECK) g[h] = vown[h] ? a.gin[i] : 0.f;
+      else g[h] = vown[h] ? ld_real<BF>(a.rbuf, i) : 0.f;
+      uu[h] = (a.u && vown[h]) ? ld_real<BF>(a.u, i) : 1.0f;
+      xp[h] = (a.xprev && vown[h]) ? a.xprev[i] : 0.f;
     }
   };
   auto store_plane = [&](int buf, const RawX* own, const RawX& halo, double* ys, double* xks) {
@@ -718,7 +766,7 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
     }
   };
 
-  double acc_l1 = 0.0, acc_hub = 0.0, acc_tv0 = 0.0, acc_kkt = 0.0, acc_x2 = 0.0;
+  double acc_l1 = 0.0, acc_hub = 0.0, acc_tv0 = 0.0, acc_kkt = 0.0, acc_x2 = 0.0, acc_gam = 0.0;
   // p on the (TX+1) x (TY+1) points of a plane from y planes yn (this plane) and yp (below).
   auto compute_p = [&](int yn, int yp, int dst, const float* vv, bool count) {
 #pragma unroll
@@ -730,14 +778,16 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
       const float dxv = yc - sY[yn][ly + 1][lx];
       const float dyv = yc - sY[yn][ly][lx + 1];
       const float dzv = yc - sY[yp][ly + 1][lx + 1];
-      const float n = sqrtf(dxv * dxv + dyv * dyv + dzv * dzv);
-      const float sc = vv[t] / fmaxf(a.eps, n);
+      // v / max(eps, |Dy|) with one reciprocal square root
+      const float n2 = dxv * dxv + dyv * dyv + dzv * dzv;
+      const float inv = n2 > a.eps * a.eps ? rsqrtf(n2) : 1.0f / a.eps;
+      const float sc = vv[t] * inv;
       sP[dst][0][ly][lx] = sc * dzv;
       sP[dst][1][ly][lx] = sc * dyv;
       sP[dst][2][ly][lx] = sc * dxv;
       if constexpr (CHECK) {
         if (count && lx < TX && ly < TY && (x0 + lx) < nx && (y0 + ly) < ny) {
-          const double nd = n;
+          const double nd = sqrt((double)n2);
           const double e = a.eps;
           const double hub = nd < e ? nd * nd / (2.0 * e) : nd - 0.5 * e;
           acc_hub += (double)vv[t] * hub;
@@ -751,7 +801,7 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
   RawX rown[2], rhalo;
   float rv[NPP];
   double own_y[2], own_xk[2], nxt_y[2], nxt_xk[2];
-  float g_cur[2], u_cur[2];
+  float g_cur[2], u_cur[2], xp_cur[2];
   {
     double dy_[2], dx_[2];
     fetch_plane(z0 - 1, rown, rhalo, rv);
@@ -759,7 +809,7 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
     fetch_plane(z0, rown, rhalo, rv);
     store_plane(1, rown, rhalo, own_y, own_xk);
   }
-  fetch_out(z0, g_cur, u_cur);
+  fetch_out(z0, g_cur, u_cur, xp_cur);
   __syncthreads();
   compute_p(1, 0, 0, rv, true);
   fetch_plane(z0 + 1, rown, rhalo, rv);
@@ -772,10 +822,11 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
 #pragma unroll
     for (int t = 0; t < NPP; ++t) vv_use[t] = rv[t];
     float g_use[2] = {g_cur[0], g_cur[1]}, u_use[2] = {u_cur[0], u_cur[1]};
+    float xp_use[2] = {xp_cur[0], xp_cur[1]};
     // prefetch plane z+2 and the outputs' inputs of plane z+1
     if (z + 1 < z1) {
       fetch_plane(z + 2, rown, rhalo, rv);
-      fetch_out(z + 1, g_cur, u_cur);
+      fetch_out(z + 1, g_cur, u_cur, xp_cur);
     }
     __syncthreads();
     compute_p(ycur ^ 1, ycur, cur ^ 1, vv_use, (z + 1) < z1);
@@ -790,9 +841,11 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
         const long long i = pz + own_off[h];
         const float gd = g_use[h];
         const float uu = u_use[h];
+        const float xp = xp_use[h];
         if constexpr (COMP) {
           const double y = own_y[h];
-          const double zv = y - a.lr * ((double)gd + a.mu * (double)gtv);
+          const double dprior = y - (double)xp;
+          const double zv = y - a.lr * ((double)gd + a.mu * (double)gtv + 2.0 * a.gamma * dprior);
           const double t = a.lr * a.lam * (double)uu;
           const double az = fabs(zv) - t;
           const double xn = az > 0.0 ? copysign(az, zv) : 0.0;
@@ -800,6 +853,7 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
             acc_l1 += (double)uu * fabs(y);
             acc_kkt += (y - xn) * (y - xn);
             acc_x2 += y * y;
+            acc_gam += dprior * dprior;
           } else {
             const float hi = (float)xn;
             const uint16_t lo = f32_to_bf16((float)(xn - (double)hi));
@@ -807,11 +861,12 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
             a.xn_lo[i] = lo;
             const double xs = (double)hi + (double)bf16_to_f32(lo);
             const double yn = xs + a.m_next * (xs - own_xk[h]);
-            a.rbuf[i] = (float)yn;
+            st_real<false>(a.rbuf, i, (float)yn);
           }
         } else {
           const float y = (float)own_y[h];
-          const float zv = y - (float)a.lr * (gd + (float)a.mu * gtv);
+          const float dprior = y - xp;
+          const float zv = y - (float)a.lr * (gd + (float)a.mu * gtv + 2.0f * (float)a.gamma * dprior);
           const float t = (float)a.lr * (float)a.lam * uu;
           const float az = fabsf(zv) - t;
           const float xn = az > 0.f ? copysignf(az, zv) : 0.f;
@@ -819,10 +874,11 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
             acc_l1 += (double)uu * fabs((double)y);
             acc_kkt += ((double)y - xn) * ((double)y - xn);
             acc_x2 += (double)y * y;
+            acc_gam += (double)dprior * dprior;
           } else {
             a.xn_hi[i] = xn;
             const float xk = (float)own_xk[h];
-            a.rbuf[i] = xn + (float)a.m_next * (xn - xk);
+            st_real<BF>(a.rbuf, i, xn + (float)a.m_next * (xn - xk));
           }
         }
       }
@@ -838,37 +894,50 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
     const int nb = gridDim.x;
     double r;
     r = block_reduce<RED_OP_SUM>(acc_l1, s_red);
-    if (tid == 0) a.partials[0 * nb + blockIdx.x] = r;
+    if (tid == 0) a.partials[0 * nb + blk] = r;
     r = block_reduce<RED_OP_SUM>(acc_hub, s_red);
-    if (tid == 0) a.partials[1 * nb + blockIdx.x] = r;
+    if (tid == 0) a.partials[1 * nb + blk] = r;
     r = block_reduce<RED_OP_SUM>(acc_tv0, s_red);
-    if (tid == 0) a.partials[2 * nb + blockIdx.x] = r;
+    if (tid == 0) a.partials[2 * nb + blk] = r;
     r = block_reduce<RED_OP_SUM>(acc_kkt, s_red);
-    if (tid == 0) a.partials[3 * nb + blockIdx.x] = r;
+    if (tid == 0) a.partials[3 * nb + blk] = r;
     r = block_reduce<RED_OP_SUM>(acc_x2, s_red);
-    if (tid == 0) a.partials[4 * nb + blockIdx.x] = r;
+    if (tid == 0) a.partials[4 * nb + blk] = r;
+    r = block_reduce<RED_OP_SUM>(acc_gam, s_red);
+    if (tid == 0) a.partials[5 * nb + blk] = r;
   }
 }
 
 // ---------------------------------------------------------------- elementwise kernels
 
-template <bool COMP>
-__global__ void k_prime(float* __restrict__ rbuf, const float* __restrict__ xk_hi, const uint16_t* __restrict__ xk_lo,
+// y = x_k + m (x_k - x_{k-1}) into the map buffer (the first x-axis transform of a round).
+template <int ST>
+__global__ void k_prime(void* __restrict__ rbuf, const float* __restrict__ xk_hi, const uint16_t* __restrict__ xk_lo,
                         const float* __restrict__ xo_hi, const uint16_t* __restrict__ xo_lo, double m, int read_old,
                         long long n) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    if constexpr (COMP) {
+    if constexpr (ST == ST_COMP) {
       const double xk = load_x<true>(xk_hi, xk_lo, i);
       double y = xk;
       if (read_old) y = xk + m * (xk - load_x<true>(xo_hi, xo_lo, i));
-      rbuf[i] = (float)y;
+      st_real<false>(rbuf, i, (float)y);
     } else {
       const float xk = xk_hi[i];
       float y = xk;
       if (read_old) y = xk + (float)m * (xk - xo_hi[i]);
-      rbuf[i] = y;
+      st_real<ST == ST_BF16>(rbuf, i, y);
     }
   }
+}
+
+__global__ void k_f32_to_bf16(const float* __restrict__ src, uint16_t* __restrict__ dst, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = f32_to_bf16(src[i]);
+}
+
+__global__ void k_bf16_to_f32(const uint16_t* __restrict__ src, float* __restrict__ dst, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = bf16_to_f32(src[i]);
 }
 
 __global__ void k_set_map(const float* __restrict__ x0, float* __restrict__ hi, uint16_t* __restrict__ lo, long long n) {
@@ -895,8 +964,9 @@ __global__ void k_fill(float* __restrict__ dst, long long n, float value) {
 // stored scaled for unnormalised transforms: ws = w~ / nvox, cs = c / sqrt(nvox).
 // Partial: max w~.
 __global__ void __launch_bounds__(256) k_fold(Dims d, const float* __restrict__ w, const float2* __restrict__ b,
-                                              float* __restrict__ ws, float* __restrict__ wnyq,
-                                              float2* __restrict__ cs, float2* __restrict__ cnyq,
+                                              float* __restrict__ ws, float* __restrict__ w0p,
+                                              float* __restrict__ wnyq, float2* __restrict__ cs,
+                                              float2* __restrict__ c0p, float2* __restrict__ cnyq,
                                               double* __restrict__ partials) {
   __shared__ double s_red[8];
   const int P = d.P;
@@ -918,14 +988,20 @@ __global__ void __launch_bounds__(256) k_fold(Dims d, const float* __restrict__ 
     const double cr = 0.5 * (wk * bk.x + wn * bn.x);
     const double ci = 0.5 * (wk * bk.y - wn * bn.y);
     mx = wt > mx ? wt : mx;
+    const float wsv = (float)(wt * inv_n);
+    const float2 csv = make_float2((float)(cr * inv_sqrt_n), (float)(ci * inv_sqrt_n));
+    const long long op = (long long)ky * d.nz + kz;  // [ky][kz] planes of kx = 0 and nx/2
     if (kx < P) {
       const long long o = ((long long)kz * d.ny + ky) * P + kx;
-      ws[o] = (float)(wt * inv_n);
-      cs[o] = make_float2((float)(cr * inv_sqrt_n), (float)(ci * inv_sqrt_n));
+      ws[o] = wsv;
+      cs[o] = csv;
+      if (kx == 0) {
+        w0p[op] = wsv;
+        c0p[op] = csv;
+      }
     } else {
-      const long long o = (long long)kz * d.ny + ky;
-      wnyq[o] = (float)(wt * inv_n);
-      cnyq[o] = make_float2((float)(cr * inv_sqrt_n), (float)(ci * inv_sqrt_n));
+      wnyq[op] = wsv;
+      cnyq[op] = csv;
     }
   }
   const double r = block_reduce<RED_OP_MAX>(mx, s_red);
@@ -981,9 +1057,9 @@ __global__ void __launch_bounds__(256) k_weight_stats(long long n, const float* 
 
 // Reweighting of eq 11 from the current map: u = 1/(|x| + eps1), v = 1/(|Dx| + eps2),
 // with |Dx| the periodic backward-difference gradient norm of eq 12.  Partial: max v.
-template <bool COMP>
+template <bool COMP, bool BF>
 __global__ void __launch_bounds__(256) k_reweight(Dims d, const float* __restrict__ hi, const uint16_t* __restrict__ lo,
-                                                  float* __restrict__ u, float* __restrict__ v, double eps1,
+                                                  void* __restrict__ u, void* __restrict__ v, double eps1,
                                                   double eps2, double* __restrict__ partials) {
   __shared__ double s_red[8];
   double mx = 0.0;
@@ -1001,9 +1077,10 @@ __global__ void __launch_bounds__(256) k_reweight(Dims d, const float* __restric
     const double ddy = xc - load_x<COMP>(hi, lo, iym);
     const double ddz = xc - load_x<COMP>(hi, lo, izm);
     const double nrm = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
-    u[i] = (float)(1.0 / (fabs(xc) + eps1));
-    const float vv = (float)(1.0 / (nrm + eps2));
-    v[i] = vv;
+    st_real<BF>(u, i, (float)(1.0 / (fabs(xc) + eps1)));
+    const float vf = (float)(1.0 / (nrm + eps2));
+    const float vv = BF ? bf16_to_f32(f32_to_bf16(vf)) : vf;  // max of the stored values
+    st_real<BF>(v, i, vf);
     mx = (double)vv > mx ? (double)vv : mx;
   }
   const double r = block_reduce<RED_OP_MAX>(mx, s_red);
@@ -1091,42 +1168,50 @@ hipError_t launch_fft_cols(const Dims& d, float2* S, int axis, int mode, const f
   return hipGetLastError();
 }
 
-hipError_t launch_dc_nyquist(const Dims& d, float2* S, const float2* tw_z, const float* ws, const float* wnyq,
-                             const float2* cs, const float2* cnyq, double* partials, hipStream_t st, int* nblocks_out) {
+hipError_t launch_dc_nyquist(const Dims& d, float2* S, const float2* tw_z, const float* w0p, const float* wnyq,
+                             const float2* c0p, const float2* cnyq, double* partials, hipStream_t st, int* nblocks_out) {
   const int L = d.nz;
   const int T = tpt(L);
   if (T == 0) return hipErrorInvalidValue;
   const dim3 grid(d.ny / 2 + 1), block(2 * T);
   if (nblocks_out) *nblocks_out = d.ny / 2 + 1;
   if (partials) {
-    SPG_DISPATCH_L(L, (k_dc_nyquist<L_, true><<<grid, block, 0, st>>>(S, d.P, d.ny, tw_z, ws, wnyq, cs, cnyq, partials)));
+    SPG_DISPATCH_L(L, (k_dc_nyquist<L_, true><<<grid, block, 0, st>>>(S, d.P, d.ny, tw_z, w0p, wnyq, c0p, cnyq, partials)));
   } else {
-    SPG_DISPATCH_L(L, (k_dc_nyquist<L_, false><<<grid, block, 0, st>>>(S, d.P, d.ny, tw_z, ws, wnyq, cs, cnyq, partials)));
+    SPG_DISPATCH_L(L, (k_dc_nyquist<L_, false><<<grid, block, 0, st>>>(S, d.P, d.ny, tw_z, w0p, wnyq, c0p, cnyq, partials)));
   }
   return hipGetLastError();
 }
 
-hipError_t launch_r2c_x(const Dims& d, const float* rin, float2* S, const float2* tw_m, const float2* tw_n,
-                        hipStream_t st) {
+hipError_t launch_r2c_x(const Dims& d, const void* rin, bool rin_bf16, float2* S, const float2* tw_m,
+                        const float2* tw_n, hipStream_t st) {
   const int M = d.P;
   const int T = tpt(M);
   if (T == 0) return hipErrorInvalidValue;
   const int NR = 256 / T < 16 ? 256 / T : 16;
   const int nrows = d.ny * d.nz;
   const dim3 grid((nrows + NR - 1) / NR), block(NR * T);
-  SPG_DISPATCH_L(M, (k_r2c_x<L_><<<grid, block, 0, st>>>(rin, S, nrows, tw_m, tw_n, NR)));
+  if (rin_bf16) {
+    SPG_DISPATCH_L(M, (k_r2c_x<L_, true><<<grid, block, 0, st>>>(rin, S, nrows, tw_m, tw_n, NR)));
+  } else {
+    SPG_DISPATCH_L(M, (k_r2c_x<L_, false><<<grid, block, 0, st>>>(rin, S, nrows, tw_m, tw_n, NR)));
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_c2r_x(const Dims& d, const float2* S, float* rout, const float2* tw_m, const float2* tw_n,
-                        hipStream_t st) {
+hipError_t launch_c2r_x(const Dims& d, const float2* S, void* rout, bool rout_bf16, const float2* tw_m,
+                        const float2* tw_n, hipStream_t st) {
   const int M = d.P;
   const int T = tpt(M);
   if (T == 0) return hipErrorInvalidValue;
   const int NR = 256 / T < 16 ? 256 / T : 16;
   const int nrows = d.ny * d.nz;
   const dim3 grid((nrows + NR - 1) / NR), block(NR * T);
-  SPG_DISPATCH_L(M, (k_c2r_x<L_><<<grid, block, 0, st>>>(S, rout, nrows, tw_m, tw_n, NR)));
+  if (rout_bf16) {
+    SPG_DISPATCH_L(M, (k_c2r_x<L_, true><<<grid, block, 0, st>>>(S, rout, nrows, tw_m, tw_n, NR)));
+  } else {
+    SPG_DISPATCH_L(M, (k_c2r_x<L_, false><<<grid, block, 0, st>>>(S, rout, nrows, tw_m, tw_n, NR)));
+  }
   return hipGetLastError();
 }
 
@@ -1137,17 +1222,20 @@ int prox_num_blocks(const Dims& d) {
   return ntx * nty * ntz;
 }
 
-hipError_t launch_prox_tv(const Dims& d, const ProxArgs& a, bool compensated, bool check, hipStream_t st) {
+hipError_t launch_prox_tv(const Dims& d, const ProxArgs& a, int store, bool check, hipStream_t st) {
   const int ntx = (d.nx + PT_TX - 1) / PT_TX;
   const int nty = (d.ny + PT_TY - 1) / PT_TY;
   const dim3 grid(prox_num_blocks(d)), block(256);
-  if (compensated) {
-    if (check) k_prox_tv<true, true><<<grid, block, 0, st>>>(a, ntx, nty);
-    else k_prox_tv<true, false><<<grid, block, 0, st>>>(a, ntx, nty);
-  } else {
-    if (check) k_prox_tv<false, true><<<grid, block, 0, st>>>(a, ntx, nty);
-    else k_prox_tv<false, false><<<grid, block, 0, st>>>(a, ntx, nty);
+#define SPG_PROX(ST_) \
+  do { if (check) k_prox_tv<ST_, true><<<grid, block, 0, st>>>(a, ntx, nty); \
+       else k_prox_tv<ST_, false><<<grid, block, 0, st>>>(a, ntx, nty); } while (0)
+  switch (store) {
+    case ST_PLAIN: SPG_PROX(ST_PLAIN); break;
+    case ST_COMP: SPG_PROX(ST_COMP); break;
+    case ST_BF16: SPG_PROX(ST_BF16); break;
+    default: return hipErrorInvalidValue;
   }
+#undef SPG_PROX
   return hipGetLastError();
 }
 
@@ -1158,12 +1246,22 @@ static dim3 ew_grid(long long n) {
   return dim3((unsigned)g);
 }
 
-hipError_t launch_prime(const Dims& d, float* rbuf, const float* xk_hi, const uint16_t* xk_lo, const float* xo_hi,
-                        const uint16_t* xo_lo, double m, int read_old, bool compensated, hipStream_t st) {
-  if (compensated)
-    k_prime<true><<<ew_grid(d.nvox), 256, 0, st>>>(rbuf, xk_hi, xk_lo, xo_hi, xo_lo, m, read_old, d.nvox);
-  else
-    k_prime<false><<<ew_grid(d.nvox), 256, 0, st>>>(rbuf, xk_hi, xk_lo, xo_hi, xo_lo, m, read_old, d.nvox);
+hipError_t launch_prime(const Dims& d, void* rbuf, const float* xk_hi, const uint16_t* xk_lo, const float* xo_hi,
+                        const uint16_t* xo_lo, double m, int read_old, int store, hipStream_t st) {
+  const dim3 g = ew_grid(d.nvox);
+  if (store == ST_COMP) k_prime<ST_COMP><<<g, 256, 0, st>>>(rbuf, xk_hi, xk_lo, xo_hi, xo_lo, m, read_old, d.nvox);
+  else if (store == ST_BF16) k_prime<ST_BF16><<<g, 256, 0, st>>>(rbuf, xk_hi, xk_lo, xo_hi, xo_lo, m, read_old, d.nvox);
+  else k_prime<ST_PLAIN><<<g, 256, 0, st>>>(rbuf, xk_hi, xk_lo, xo_hi, xo_lo, m, read_old, d.nvox);
+  return hipGetLastError();
+}
+
+hipError_t launch_f32_to_bf16(const float* src, uint16_t* dst, long long n, hipStream_t st) {
+  k_f32_to_bf16<<<ew_grid(n), 256, 0, st>>>(src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_bf16_to_f32(const uint16_t* src, float* dst, long long n, hipStream_t st) {
+  k_bf16_to_f32<<<ew_grid(n), 256, 0, st>>>(src, dst, n);
   return hipGetLastError();
 }
 
@@ -1184,9 +1282,9 @@ hipError_t launch_fill(float* dst, long long n, float value, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_fold(const Dims& d, const float* w, const float2* b, float* ws, float* wnyq, float2* cs,
-                       float2* cnyq, double* partials, int nblocks, hipStream_t st) {
-  k_fold<<<nblocks, 256, 0, st>>>(d, w, b, ws, wnyq, cs, cnyq, partials);
+hipError_t launch_fold(const Dims& d, const float* w, const float2* b, float* ws, float* w0p, float* wnyq,
+                       float2* cs, float2* c0p, float2* cnyq, double* partials, int nblocks, hipStream_t st) {
+  k_fold<<<nblocks, 256, 0, st>>>(d, w, b, ws, w0p, wnyq, cs, c0p, cnyq, partials);
   return hipGetLastError();
 }
 
@@ -1201,10 +1299,11 @@ hipError_t launch_weight_stats(const Dims& d, const float* a, double* partials, 
   return hipGetLastError();
 }
 
-hipError_t launch_reweight(const Dims& d, const float* hi, const uint16_t* lo, float* u, float* v, double eps1,
-                           double eps2, bool compensated, double* partials, int nblocks, hipStream_t st) {
-  if (compensated) k_reweight<true><<<nblocks, 256, 0, st>>>(d, hi, lo, u, v, eps1, eps2, partials);
-  else k_reweight<false><<<nblocks, 256, 0, st>>>(d, hi, lo, u, v, eps1, eps2, partials);
+hipError_t launch_reweight(const Dims& d, const float* hi, const uint16_t* lo, void* u, void* v, double eps1,
+                           double eps2, int store, double* partials, int nblocks, hipStream_t st) {
+  if (store == ST_COMP) k_reweight<true, false><<<nblocks, 256, 0, st>>>(d, hi, lo, u, v, eps1, eps2, partials);
+  else if (store == ST_BF16) k_reweight<false, true><<<nblocks, 256, 0, st>>>(d, hi, lo, u, v, eps1, eps2, partials);
+  else k_reweight<false, false><<<nblocks, 256, 0, st>>>(d, hi, lo, u, v, eps1, eps2, partials);
   return hipGetLastError();
 }
 

@@ -20,6 +20,7 @@ SPG_OK = 0
 STATUS_NAMES = {0: "SPG_OK", -1: "SPG_E_INVAL", -2: "SPG_E_NOMEM", -3: "SPG_E_DEVICE", -4: "SPG_E_STATE",
                 -5: "SPG_E_NONFINITE", -6: "SPG_E_DIVERGED", -7: "SPG_E_UNSUPPORTED"}
 FLAG_COMPENSATED = 1
+FLAG_BF16_STORAGE = 2
 
 KERNELS = ["fft_y_fwd", "fft_z_weight", "dc_nyquist", "fft_y_inv", "c2r_x", "prox_tv", "r2c_x"]
 
@@ -60,6 +61,7 @@ def lib() -> ctypes.CDLL:
         "spg_set_penalty_weights": [P, P, P],
         "spg_set_params": [P, c_double, c_double],
         "spg_set_map": [P, P],
+        "spg_set_prior": [P, c_double, P],
         "spg_run": [P, c_int32, POINTER(Stats)],
         "spg_reweight": [P, c_double, c_double],
         "spg_get_map": [P, P],
@@ -83,14 +85,19 @@ def lib() -> ctypes.CDLL:
     return L
 
 
-def make_params(shape, lam, mu, eps, accel=True, compensated=True, gamma=0.0) -> Params:
+STORAGE = {"compensated": FLAG_COMPENSATED, "fp32": 0, "bf16": FLAG_BF16_STORAGE}
+
+
+def make_params(shape, lam, mu, eps, accel=True, compensated=True, gamma=0.0, storage=None) -> Params:
+    """storage: 'compensated' (default), 'fp32' or 'bf16'; `compensated=False` means 'fp32'."""
     nz, ny, nx = (int(s) for s in shape)
-    return Params(nx, ny, nz, float(lam), float(mu), float(eps), float(gamma), 1 if accel else 0,
-                  FLAG_COMPENSATED if compensated else 0)
+    if storage is None:
+        storage = "compensated" if compensated else "fp32"
+    return Params(nx, ny, nz, float(lam), float(mu), float(eps), float(gamma), 1 if accel else 0, STORAGE[storage])
 
 
-def workspace_size(shape, lam=0.01, mu=0.05, eps=1e-3, accel=True, compensated=True, gamma=0.0) -> int:
-    p = make_params(shape, lam, mu, eps, accel, compensated, gamma)
+def workspace_size(shape, lam=0.01, mu=0.05, eps=1e-3, accel=True, compensated=True, gamma=0.0, storage=None) -> int:
+    p = make_params(shape, lam, mu, eps, accel, compensated, gamma, storage)
     n = c_size_t(0)
     st = lib().spg_workspace_size(byref(p), byref(n))
     if st != SPG_OK:
@@ -118,16 +125,17 @@ class SPGSolver:
     b as complex64 (nz, ny, nx), FFT order.
     """
 
-    def __init__(self, shape, lam, mu, eps, accel=True, compensated=True, device="cuda", stream=None):
+    def __init__(self, shape, lam, mu, eps, accel=True, compensated=True, device="cuda", stream=None, storage=None,
+                 gamma=0.0):
         import torch
 
         self.torch = torch
         self.shape = tuple(int(s) for s in shape)
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.compensated = compensated
+        self.storage = storage if storage is not None else ("compensated" if compensated else "fp32")
         self._L = lib()
-        p = make_params(self.shape, lam, mu, eps, accel, compensated)
+        p = make_params(self.shape, lam, mu, eps, accel, compensated, gamma, self.storage)
         n = c_size_t(0)
         self._check(self._L.spg_workspace_size(byref(p), byref(n)), None)
         self.ws_bytes = int(n.value)
@@ -176,6 +184,12 @@ class SPGSolver:
 
     def set_params(self, lam, mu):
         self._check(self._L.spg_set_params(self._h, float(lam), float(mu)))
+
+    def set_prior(self, gamma, x_prev=None):
+        """gamma |x - x_prev|^2 of eq 22 (x_prev None = zero map)."""
+        x_prev = self._dev(x_prev, self.torch.float32)
+        self._check(self._L.spg_set_prior(self._h, float(gamma), _ptr(x_prev)))
+        self._keep = [x_prev]
 
     def set_map(self, x0=None):
         x0 = self._dev(x0, self.torch.float32)
@@ -249,9 +263,9 @@ class SPGSolver:
 
 
 def solve(vol_w, vol_b, shape, lam, mu, eps, rounds, iters, eps1, eps2, accel=True, compensated=True,
-          x0=None, device="cuda") -> "SPGSolver":
+          x0=None, device="cuda", storage=None) -> "SPGSolver":
     """Reweighting schedule: round 1 with u = v = 1, then eq 11 weights before each later round."""
-    s = SPGSolver(shape, lam, mu, eps, accel=accel, compensated=compensated, device=device)
+    s = SPGSolver(shape, lam, mu, eps, accel=accel, compensated=compensated, device=device, storage=storage)
     s.set_data(vol_w, vol_b)
     s.set_map(x0)
     for r in range(rounds):

@@ -47,9 +47,25 @@ def test_workspace_size_model():
     n = nx * ny * nz
     b = _ws((nz, ny, nx))
     # 3 fp32 + 3 bf16 iterate slots, u, v, spectrum, gradient map, folded weights and data
-    core = 3 * 4 * n + 3 * 2 * n + 2 * 4 * n + 4 * n + 4 * n + 2 * n + 4 * n
+    # 3 fp32 + 3 bf16 iterate slots, u, v, spectrum, map buffer, prior map, folded weights and data
+    core = 3 * 4 * n + 3 * 2 * n + 2 * 4 * n + 4 * n + 4 * n + 4 * n + 2 * n + 4 * n
     assert core <= b <= core + 2 * 1024 * 1024
-    assert _ws((nz, ny, nx), compensated=False) < b
+    assert _ws((nz, ny, nx), compensated=False) == b - 3 * 2 * n
+    # bf16 storage: u, v and the map buffer at 2 bytes
+    assert _ws((nz, ny, nx), storage="bf16") == b - 3 * 2 * n - 3 * 2 * n
+
+
+def test_storage_flags_are_exclusive(L):
+    p = spg.make_params((8, 8, 8), 0.01, 0.05, 1e-3)
+    p.flags = spg.FLAG_COMPENSATED | spg.FLAG_BF16_STORAGE
+    n = ctypes.c_size_t()
+    assert L.spg_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1
+    p.flags = 4
+    assert L.spg_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1
+
+
+def test_gamma_is_accepted():
+    assert _ws((8, 8, 8), gamma=0.3) == _ws((8, 8, 8))
 
 
 @pytest.mark.parametrize("shape", [(3, 4, 4), (4, 4, 2), (1024, 4, 4), (4, 6, 4), (0, 4, 4)])
@@ -60,8 +76,8 @@ def test_rejects_bad_grids(shape):
 
 
 @pytest.mark.parametrize("kw,code", [(dict(lam=-1.0), -1), (dict(mu=-0.1), -1), (dict(eps=0.0), -1),
-                                     (dict(eps=float("nan")), -1), (dict(gamma=0.1), -7),
-                                     (dict(gamma=-0.1), -1)])
+                                     (dict(eps=float("nan")), -1), (dict(gamma=-0.1), -1),
+                                     (dict(gamma=float("inf")), -1)])
 def test_rejects_bad_params(kw, code):
     with pytest.raises(spg.SPGError) as e:
         _ws((8, 8, 8), **kw)

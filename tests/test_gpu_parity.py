@@ -254,3 +254,82 @@ def test_full_size_512_one_step_vs_oracle():
     err = rel_l2(x, xo)
     print(f"512^3 one-step rel L2 = {err:.3e}", flush=True)
     assert err < TOL
+
+
+# ------------------------------------------------------------------ gamma term (eq 22)
+
+@pytest.mark.parametrize("storage", ["compensated", "fp32"])
+def test_gamma_prior_term_parity(storage):
+    shape = (16, 32, 64)
+    announce(f"gamma term parity storage={storage}")
+    w, b, u, v, x0 = _rand_inputs(shape, 21)
+    rng = np.random.default_rng(np.random.SeedSequence([21, 99]))
+    xprev = (rng.standard_normal(shape) * 0.2).astype(np.float32)
+    lam, mu, eps, gamma = 0.02, 0.05, 1e-2, 0.3
+    s = spg.SPGSolver(shape, lam, mu, eps, storage=storage)
+    s.set_data(w, b)
+    s.set_penalty_weights(u, v)
+    s.set_prior(gamma, xprev)
+    s.set_map(x0)
+    s.run(25)
+    x = to_np(s.get_map())
+    p = oracle_problem(w, b, lam, mu, eps, u=u, v=v)
+    p.gamma = gamma
+    p.x_prev = xprev.astype(np.float64)
+    xo = O.spg_solve(p, 25, x0=x0.astype(np.float64))
+    err = rel_l2(x, xo)
+    print(f"gamma {storage}: rel L2 = {err:.3e}", flush=True)
+    assert err < TOL
+    fe, f0, kkt = s.final_check()
+    ofe = O.objective(x, p)
+    assert abs(fe - ofe) <= 1e-6 * abs(ofe)
+    assert abs(kkt - O.kkt_residual(x, p)) <= 1e-3 * kkt + 1e-7
+
+
+# ------------------------------------------------------------------ bf16 storage (growth)
+
+BF16_TOL = 1e-3
+
+
+def test_bf16_storage_schedule_within_bar():
+    cfg = synth.scaled_config((64, 64, 64), iters=40)
+    vol, c = synth.make_config(cfg)
+    announce("bf16 storage: 64^3, 3 rounds x 40")
+    s = spg.SPGSolver(c["shape"], c["lam"], c["mu"], c["eps"], storage="bf16")
+    s.set_data(vol.w, vol.b)
+    s.set_map(None)
+    p = oracle_problem(vol.w, vol.b, c["lam"], c["mu"], c["eps"])
+    xo, _, _ = O.solve_schedule(p, 3, c["iters"], c["eps1"], c["eps2"])
+    for r in range(3):
+        if r > 0:
+            s.reweight(c["eps1"], c["eps2"])
+        s.run(c["iters"])
+    err = rel_l2(to_np(s.get_map()), xo)
+    print(f"bf16 storage 3x{c['iters']} rel L2 = {err:.3e}", flush=True)
+    assert err < BF16_TOL
+    fe, f0, kkt = s.final_check()
+    x = to_np(s.get_map())
+    u, v = s.get_penalty_weights()
+    pp = oracle_problem(vol.w, vol.b, c["lam"], c["mu"], c["eps"], u=to_np(u), v=to_np(v))
+    assert abs(fe - O.objective(x, pp)) <= 1e-6 * abs(fe)
+
+
+def test_bf16_storage_weighted_ragged_and_deterministic():
+    shape = (16, 8, 128)
+    announce("bf16 storage: weighted u,v, ragged grid, determinism")
+    w, b, u, v, x0 = _rand_inputs(shape, 23)
+    outs = []
+    for _ in range(2):
+        s = spg.SPGSolver(shape, 0.02, 0.05, 1e-2, storage="bf16")
+        s.set_data(w, b)
+        s.set_penalty_weights(u, v)
+        s.set_map(x0)
+        s.run(25)
+        outs.append(s.get_map())
+    assert torch.equal(outs[0], outs[1])
+    ub = torch.from_numpy(u).to(torch.bfloat16).float().numpy()
+    vb = torch.from_numpy(v).to(torch.bfloat16).float().numpy()
+    p = oracle_problem(w, b, 0.02, 0.05, 1e-2, u=ub, v=vb)
+    err = rel_l2(to_np(outs[0]), O.spg_solve(p, 25, x0=x0.astype(np.float64)))
+    print(f"bf16 weighted rel L2 = {err:.3e}", flush=True)
+    assert err < BF16_TOL
