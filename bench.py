@@ -21,37 +21,45 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "SPG iterations/sec and HBM GB/s at 512^3 FP32 (rel. L2 ≤1e-5 vs FP64 oracle)"
+# measured HBM bytes per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, copy-calibrated)
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "hbm_traffic_solve_512.txt")
 HBM_PEAK_GBPS = 8000.0
 
 
-def kernel_bytes(shape, compensated=True):
+def kernel_bytes(shape, storage="compensated"):
     """Algorithmic HBM bytes per launch of each kernel class (each array read or written once).
 
     Returned as functions of the launch kind where the traffic depends on it (the stencil
     kernel reads x_{k-1} only when the momentum is non-zero and u, v only when explicit).
+    Storage: 'compensated' (fp32 + bf16 iterate words), 'fp32', or 'bf16' (fp32 iterate,
+    bf16 penalty weights and gradient / extrapolated map).
     """
     nz, ny, nx = shape
     n = nx * ny * nz
     spec = 4 * n           # packed half spectrum, complex64: nz*ny*(nx/2)*8
-    xb = 6 if compensated else 4
+    xb = 6 if storage == "compensated" else 4
+    rb = 2 if storage == "bf16" else 4    # map buffer and penalty weights
     col = ny * nz
     return {
         "fft_y_fwd": 2 * spec,
         "fft_z_weight": 2 * spec + spec // 2 + spec,          # S in/out, w~ (fp32), c (complex64)
         "dc_nyquist": col * (8 + 4 + 4 + 8 + 8 + 8),           # the packed kx=0 column in/out + its weights
         "fft_y_inv": 2 * spec,
-        "c2r_x": spec + 4 * n,
-        "r2c_x": 4 * n + spec,
+        "c2r_x": spec + rb * n,
+        "r2c_x": rb * n + spec,
         # gradient map in, y' out, x_k in, x_{k+1} out, [x_{k-1} in], [u, v in]
-        "prox_tv": lambda momentum, explicit_uv: (4 + 4 + xb + xb + (xb if momentum else 0)
-                                                  + (8 if explicit_uv else 0)) * n,
-        "prox_tv_check": lambda explicit_uv: (4 + xb + (8 if explicit_uv else 0)) * n,
+        "prox_tv": lambda momentum, explicit_uv: (rb + rb + xb + xb + (xb if momentum else 0)
+                                                  + (2 * rb if explicit_uv else 0)) * n,
+        # check mode: fp32 gradient in, x in, [u, v in]
+        "prox_tv_check": lambda explicit_uv: (4 + xb + (2 * rb if explicit_uv else 0)) * n,
+        "r2c_x_check": 4 * n + spec,
+        "c2r_x_check": spec + 4 * n,
     }
 
 
-def schedule_bytes(shape, rounds, iters, steps, compensated=True):
+def schedule_bytes(shape, rounds, iters, steps, storage="compensated"):
     """Total algorithmic bytes per kernel class over `steps` solves of the schedule."""
-    kb = kernel_bytes(shape, compensated)
+    kb = kernel_bytes(shape, storage)
     tot = {k: 0 for k in ["fft_y_fwd", "fft_z_weight", "dc_nyquist", "fft_y_inv", "c2r_x", "prox_tv", "r2c_x"]}
     launches = {k: 0 for k in tot}
     for _ in range(steps):
@@ -65,17 +73,21 @@ def schedule_bytes(shape, rounds, iters, steps, compensated=True):
                 launches["prox_tv"] += 1
             tot["r2c_x"] += kb["r2c_x"]      # priming transform at the start of each round
             launches["r2c_x"] += 1
-        # final check: one more forward/inverse pipeline and the stencil in check mode
-        for k in ["fft_y_fwd", "fft_z_weight", "dc_nyquist", "fft_y_inv", "c2r_x", "r2c_x"]:
+        # final check: one more forward/inverse pipeline (fp32 map in, fp32 gradient out) and
+        # the stencil in check mode
+        for k in ["fft_y_fwd", "fft_z_weight", "dc_nyquist", "fft_y_inv"]:
             tot[k] += kb[k]
+            launches[k] += 1
+        for k in ["c2r_x", "r2c_x"]:
+            tot[k] += kb[k + "_check"]
             launches[k] += 1
         tot["prox_tv"] += kb["prox_tv_check"](rounds > 1)
         launches["prox_tv"] += 1
     return tot, launches
 
 
-def iteration_bytes(shape, explicit_uv=True, compensated=True):
-    kb = kernel_bytes(shape, compensated)
+def iteration_bytes(shape, explicit_uv=True, storage="compensated"):
+    kb = kernel_bytes(shape, storage)
     return sum(kb[k] for k in ["fft_y_fwd", "fft_z_weight", "dc_nyquist", "fft_y_inv", "c2r_x", "r2c_x"]) + \
         kb["prox_tv"](True, explicit_uv)
 
@@ -121,7 +133,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--iters", type=int, default=None, help="override SPG iterations per round")
-    ap.add_argument("--plain-fp32", action="store_true", help="store the iterate as plain fp32")
+    ap.add_argument("--storage", choices=["compensated", "fp32", "bf16"], default="compensated",
+                    help="iterate / map storage mode")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel HIP events")
     ap.add_argument("--copy-calib", action="store_true", help="only run the copy kernel used to scale HBM counters")
@@ -143,7 +156,7 @@ def main():
         copy_calibration()
         return
 
-    from paper_1905_13408_amd import spg, synth
+    from paper_1905_13408_amd import profiling, spg, synth
 
     t_gen = time.perf_counter()
     vol, c = synth.make_config(args.config)
@@ -152,11 +165,11 @@ def main():
     print(f"# inputs generated in {time.perf_counter() - t_gen:.1f} s: {c['name']} {c['shape']}", file=sys.stderr,
           flush=True)
     shape = c["shape"]
-    compensated = not args.plain_fp32
+    storage = args.storage
     w = torch.from_numpy(vol.w).cuda()
     b = torch.from_numpy(vol.b).cuda()
     out = torch.empty(shape, dtype=torch.float32, device="cuda")
-    solver = spg.SPGSolver(shape, c["lam"], c["mu"], c["eps"], compensated=compensated)
+    solver = spg.SPGSolver(shape, c["lam"], c["mu"], c["eps"], storage=storage)
     rounds, iters = c["rounds"], c["iters"]
 
     result = {}
@@ -191,7 +204,7 @@ def main():
     elapsed = t1 - t0
     total_iters = rounds * iters * args.steps
     value = total_iters / elapsed
-    it_bytes = iteration_bytes(shape, True, compensated)
+    it_bytes = iteration_bytes(shape, True, storage)
     line = {
         "metric": METRIC,
         "value": value,
@@ -209,7 +222,9 @@ def main():
                                f"{c['n_chains']} chains, SNR {c['snr']}, lambda {c['lam']}, mu {c['mu']}, eps "
                                f"{c['eps']}, {rounds} rounds x {iters} SPG iterations, reweight floors "
                                f"{c['eps1']}/{c['eps2']}",
-                   "iterate_storage": "fp32 hi + bf16 lo, fp64 prox" if compensated else "fp32",
+                   "iterate_storage": {"compensated": "fp32 hi + bf16 lo iterate, fp64 prox",
+                                       "fp32": "fp32 iterate",
+                                       "bf16": "fp32 iterate, bf16 weights and map buffer"}[storage],
                    "step": "set data + solve + fetch map + fp64 objective/KKT check"},
         "ms_per_iteration": 1e3 * elapsed / total_iters,
         "model_bytes_per_iteration": it_bytes,
@@ -218,7 +233,7 @@ def main():
         "final_kkt_rel": result["check"][2],
     }
     if prof is not None:
-        tot_bytes, launches = schedule_bytes(shape, rounds, iters, args.steps, compensated)
+        tot_bytes, launches = schedule_bytes(shape, rounds, iters, args.steps, storage)
         kern = {}
         for k, (ms, n) in prof.items():
             if n:
@@ -231,8 +246,14 @@ def main():
         bytes_per_launch = tot_bytes[dom] / kern[dom]["launches"]
         t_avg = kern[dom]["ms_total"] * 1e-3 / kern[dom]["launches"]
         ach = bytes_per_launch / t_avg / 1e9
+        traffic = None
+        rec = profiling.load(TRAFFIC_RECORD) if (args.config == 3 and storage == "compensated" and
+                                                   not args.iters) else None
+        if rec and dom in rec["per_launch"]:
+            e = rec["per_launch"][dom]
+            traffic = e["fetch_bytes"] + e["write_bytes"]
         line["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                            "frac": ach / HBM_PEAK_GBPS, "traffic": None,
+                            "frac": ach / HBM_PEAK_GBPS, "traffic": traffic,
                             "bytes_per_launch": bytes_per_launch, "us_per_launch": t_avg * 1e6}
     if not args.no_cpu_baseline:
         print("# cpu baseline (FP64 oracle, one iteration)", file=sys.stderr, flush=True)

@@ -159,6 +159,40 @@ spg_status spg_state_size(const spg_problem* P, size_t* bytes);
 spg_status spg_get_state(spg_problem* P, void* d_buf, size_t bytes);
 spg_status spg_set_state(spg_problem* P, const void* d_buf, size_t bytes);
 
+/* Reverse mode of an unrolled solve, for tuning lambda, mu and the data b: the gradient of
+ * a scalar loss of x_K with respect to (lambda, mu, b) through K SPG iterations (eq 20-21
+ * with momentum, lr = 1/L(mu) differentiated as well), by the chain rule with a.e.
+ * derivatives at the soft-threshold and smoothing kinks.  Not available with
+ * SPG_FLAG_BF16_STORAGE.
+ *
+ * spg_vjp_workspace_size: bytes of the caller's reverse-pass workspace for K iterations
+ *   with a checkpoint every C iterations (1 <= C <= K): ceil(K/C)+1 ring checkpoints, C+2
+ *   fp32 maps and C data gradients of one replayed segment, and five fp32 maps.
+ * spg_run_checkpointed: restart the momentum at the current map x_0 and run K iterations,
+ *   saving the iterate ring every C iterations into d_vjp_ws (256-byte aligned).
+ * spg_vjp: given xbar = dloss/dx_K (nz*ny*nx float) and the Fourier weights w passed to
+ *   spg_set_data, replay each segment from its checkpoint and walk it backwards; writes
+ *   b_bar (nz*ny*nx complex, interleaved, FFT order; dloss = Re sum conj(b_bar) db) and the
+ *   host scalars lam_bar, mu_bar.  SPG_E_STATE if no checkpointed run matches the current
+ *   parameters.  Synchronises; leaves the problem at x_K. */
+spg_status spg_vjp_workspace_size(const spg_problem* P, int32_t K, int32_t C, size_t* bytes);
+spg_status spg_run_checkpointed(spg_problem* P, int32_t K, int32_t C, void* d_vjp_ws, size_t bytes);
+spg_status spg_vjp(spg_problem* P, void* d_vjp_ws, size_t bytes, const float* d_w, const float* d_xbar,
+                   float* d_bbar, double* lam_bar, double* mu_bar);
+
+/* Gold-standard Fourier shell correlation of eq 30 (section 2.3) between two real maps
+ * d_map1, d_map2 (nz*ny*nx float each, each axis a power of two in [4, 512]):
+ *   FSC(s) = Re sum_{k in s} F conj G / sqrt(sum_{k in s} |F|^2 sum_{k in s} |G|^2)
+ * over the full spectrum, shell s = floor(min(n) sqrt(sum_a (k_a / n_a)^2) + 1/2) of the
+ * signed frequency k (for a cubic grid the rounded |k|), s in [0, nshells), 1 <= nshells
+ * <= 1024; a shell without power in either map gives 0.  h_fsc receives nshells host
+ * doubles.  The workspace (device, 256-byte aligned, spg_fsc_workspace_size bytes) is the
+ * caller's; the call synchronises the stream.  Shell sums use fp64 atomics in LDS, so
+ * results can differ between runs in the last bits. */
+spg_status spg_fsc_workspace_size(int32_t nx, int32_t ny, int32_t nz, int32_t nshells, size_t* bytes);
+spg_status spg_fsc(int32_t nx, int32_t ny, int32_t nz, const float* d_map1, const float* d_map2, int32_t nshells,
+                   void* d_workspace, size_t bytes, void* hip_stream, double* h_fsc);
+
 /* Kernel classes for spg_profile_begin. */
 typedef enum {
   SPG_KERNEL_FFT_Y_FWD = 0, /* y-axis forward column FFT                               */

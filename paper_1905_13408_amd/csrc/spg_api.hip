@@ -4,6 +4,7 @@
 // profiling is on).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -135,6 +136,11 @@ struct spg_problem {
   double t = 1.0;        // FISTA t_j
   double m_cur = 0.0;    // momentum m_j of y_j
   char err[512] = {0};
+  // unrolled solve recorded by spg_run_checkpointed for spg_vjp
+  bool vjp_valid = false;
+  int32_t vjp_K = 0, vjp_C = 0;
+  double vjp_lr = 0;
+  std::vector<double> vjp_m;
   // profiling: events [class][launch][begin/end]
   bool prof_on = false;
   int prof_class = -1, prof_cap = 0;
@@ -186,6 +192,7 @@ void recompute_L(spg_problem* P) {
 }
 
 void restart(spg_problem* P) {
+  P->vjp_valid = false;  // a recorded unrolled solve no longer matches
   P->j = 1;
   P->t = 1.0;
   P->m_cur = 0.0;
@@ -205,6 +212,12 @@ void prof_end(spg_problem* P, int cls) {
     (void)hipEventRecord(P->ev[prof_slot(P, cls) + 1], P->stream);
     ++P->prof_n[cls];
   }
+}
+
+spg_status read_results_to(spg_problem* P, const double* dev, double* host, int n) {
+  SPG_CK(P, hipMemcpyAsync(host, dev, n * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  SPG_CK(P, hipStreamSynchronize(P->stream));
+  return SPG_OK;
 }
 
 spg_status read_results(spg_problem* P, double* host, int n) {
@@ -463,14 +476,11 @@ spg_status spg_set_map(spg_problem* P, const float* d_x0) {
   return SPG_OK;
 }
 
-spg_status spg_run(spg_problem* P, int32_t K, spg_stats* stats) {
-  spg_status s = usable(P);
-  if (s) return s;
-  if (K < 0) return set_err(P, SPG_E_INVAL, "K must be >= 0");
-  if (!P->data_set) return set_err(P, SPG_E_STATE, "spg_set_data has not succeeded");
-  if (!(P->L > 0)) return set_err(P, SPG_E_STATE, "L = 0");
+// One SPG iteration; with capture_g, the data gradient of y_k is also copied there (fp32).
+static spg_status iterate_once(spg_problem* P, float* capture_g) {
+  spg_status s;
   const Dims& d = P->d;
-  for (int it = 0; it < K; ++it) {
+  {
     if (!P->primed) {
       SPG_CK(P, launch_prime(d, P->rbuf(), P->xhi(P->cur), P->xlo(P->cur), P->xhi(P->old), P->xlo(P->old),
                              P->m_cur, P->m_cur != 0.0, P->store, P->stream));
@@ -478,6 +488,8 @@ spg_status spg_run(spg_problem* P, int32_t K, spg_stats* stats) {
       P->primed = true;
     }
     if ((s = gradient_pipeline(P, false, nullptr, nullptr, P->rbuf(), P->bf()))) return s;
+    if (capture_g)
+      SPG_CK(P, hipMemcpyAsync(capture_g, P->rbuf(), (size_t)d.nvox * 4, hipMemcpyDeviceToDevice, P->stream));
     const double t_next = P->prm.accel ? 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * P->t * P->t)) : 1.0;
     const double m_next = P->prm.accel ? (P->t - 1.0) / t_next : 0.0;
     const int nxt = 3 - P->cur - P->old;
@@ -493,6 +505,18 @@ spg_status spg_run(spg_problem* P, int32_t K, spg_stats* stats) {
     ++P->j;
     ++P->iters_done;
   }
+  return SPG_OK;
+}
+
+spg_status spg_run(spg_problem* P, int32_t K, spg_stats* stats) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if (K < 0) return set_err(P, SPG_E_INVAL, "K must be >= 0");
+  if (!P->data_set) return set_err(P, SPG_E_STATE, "spg_set_data has not succeeded");
+  if (!(P->L > 0)) return set_err(P, SPG_E_STATE, "L = 0");
+  P->vjp_valid = false;
+  for (int it = 0; it < K; ++it)
+    if ((s = iterate_once(P, nullptr))) return s;
   if (stats) {
     stats->iters_done = P->iters_done;
     stats->round = P->round;
@@ -585,6 +609,312 @@ spg_status spg_final_check(spg_problem* P, double* F_eps, double* F_0, double* k
   if (!std::isfinite(fe)) return set_err(P, SPG_E_DIVERGED, "objective is not finite");
   return SPG_OK;
 }
+
+// ---------------------------------------------------------------- Fourier shell correlation
+
+namespace {
+constexpr int kFscBlocks = 256;
+
+struct FscLayout {
+  size_t S1, S2, tw_m, tw_n, tw_y, tw_z, part, out, total;
+};
+
+FscLayout fsc_layout(int nx, int ny, int nz, int nshells) {
+  FscLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  const size_t spec = (size_t)nz * ny * (nx / 2) * 8;
+  L.S1 = take(spec);
+  L.S2 = take(spec);
+  L.tw_m = take((size_t)(nx / 2) * 8);
+  L.tw_n = take((size_t)nx * 8);
+  L.tw_y = take((size_t)ny * 8);
+  L.tw_z = take((size_t)nz * 8);
+  L.part = take((size_t)kFscBlocks * 3 * nshells * 8);
+  L.out = take((size_t)3 * nshells * 8);
+  L.total = off;
+  return L;
+}
+
+bool fsc_args_ok(int nx, int ny, int nz, int nshells) {
+  return pow2_in(nx, 4, 512) && pow2_in(ny, 4, 512) && pow2_in(nz, 4, 512) && nshells >= 1 && nshells <= 1024;
+}
+}  // namespace
+
+extern "C" {
+
+spg_status spg_fsc_workspace_size(int32_t nx, int32_t ny, int32_t nz, int32_t nshells, size_t* bytes) {
+  if (!bytes || !fsc_args_ok(nx, ny, nz, nshells)) return SPG_E_INVAL;
+  *bytes = fsc_layout(nx, ny, nz, nshells).total;
+  return SPG_OK;
+}
+
+spg_status spg_fsc(int32_t nx, int32_t ny, int32_t nz, const float* d_map1, const float* d_map2, int32_t nshells,
+                   void* d_workspace, size_t bytes, void* hip_stream, double* h_fsc) {
+  if (!fsc_args_ok(nx, ny, nz, nshells) || !d_map1 || !d_map2 || !h_fsc || !d_workspace ||
+      (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0)
+    return SPG_E_INVAL;
+  const FscLayout lay = fsc_layout(nx, ny, nz, nshells);
+  if (bytes < lay.total) return SPG_E_NOMEM;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  char* ws = reinterpret_cast<char*>(d_workspace);
+  Dims d{nx, ny, nz, nx / 2, (long long)nx * ny * nz};
+  const int lens[4] = {nx / 2, nx, ny, nz};
+  const size_t offs[4] = {lay.tw_m, lay.tw_n, lay.tw_y, lay.tw_z};
+  std::vector<float2> tab;
+  for (int t = 0; t < 4; ++t) {
+    tab.resize(lens[t]);
+    for (int m = 0; m < lens[t]; ++m) {
+      const double ang = -2.0 * M_PI * (double)m / (double)lens[t];
+      tab[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    if (hipMemcpyAsync(ws + offs[t], tab.data(), lens[t] * sizeof(float2), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return SPG_E_DEVICE;
+  }
+  const float2* twm = reinterpret_cast<const float2*>(ws + lay.tw_m);
+  const float2* twn = reinterpret_cast<const float2*>(ws + lay.tw_n);
+  const float2* twy = reinterpret_cast<const float2*>(ws + lay.tw_y);
+  const float2* twz = reinterpret_cast<const float2*>(ws + lay.tw_z);
+  const float* maps[2] = {d_map1, d_map2};
+  float2* specs[2] = {reinterpret_cast<float2*>(ws + lay.S1), reinterpret_cast<float2*>(ws + lay.S2)};
+  for (int k = 0; k < 2; ++k) {
+    if (launch_r2c_x(d, maps[k], false, specs[k], twm, twn, st) != hipSuccess) return SPG_E_DEVICE;
+    if (launch_fft_cols(d, specs[k], 1, 0, twy, nullptr, nullptr, nullptr, st, nullptr) != hipSuccess)
+      return SPG_E_DEVICE;
+    if (launch_fft_cols(d, specs[k], 2, 0, twz, nullptr, nullptr, nullptr, st, nullptr) != hipSuccess)
+      return SPG_E_DEVICE;
+  }
+  double* out = reinterpret_cast<double*>(ws + lay.out);
+  if (launch_fsc_shells(d, specs[0], specs[1], nshells, reinterpret_cast<double*>(ws + lay.part), kFscBlocks, out,
+                        st) != hipSuccess)
+    return SPG_E_DEVICE;
+  std::vector<double> h(3 * (size_t)nshells);
+  if (hipMemcpyAsync(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return SPG_E_DEVICE;
+  for (int sidx = 0; sidx < nshells; ++sidx) {
+    const double den = std::sqrt(h[nshells + sidx] * h[2 * (size_t)nshells + sidx]);
+    h_fsc[sidx] = den > 0 ? h[sidx] / den : 0.0;
+  }
+  return SPG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- reverse pass (adjoint)
+
+namespace {
+struct VjpLayout {
+  size_t ck, ck_slot, seg_x, seg_g, abar, zbar, hz, rbar, part, res, total;
+  int nseg;
+};
+
+VjpLayout vjp_layout(const spg_problem* P, int K, int C) {
+  VjpLayout L{};
+  const size_t n4 = align_up((size_t)P->d.nvox * 4);
+  const size_t n2 = P->comp ? align_up((size_t)P->d.nvox * 2) : 0;
+  L.nseg = (K + C - 1) / C;
+  L.ck_slot = 2 * (n4 + n2);  // (x_j, x_{j-1}) as hi (+ lo) words
+  size_t off = 0;
+  L.ck = off;
+  off += (size_t)(L.nseg + 1) * L.ck_slot;
+  L.seg_x = off;
+  off += (size_t)(C + 2) * n4;
+  L.seg_g = off;
+  off += (size_t)C * n4;
+  L.abar = off;
+  off += 3 * n4;
+  L.zbar = off;
+  off += n4;
+  L.hz = off;
+  off += n4;
+  L.rbar = off;
+  off += n4;
+  L.part = off;
+  off += align_up(3 * (size_t)kStatBlocks * 8);
+  L.res = off;
+  off += 256;
+  L.total = off;
+  return L;
+}
+
+// ring slots (cur, old) <-> checkpoint c
+spg_status ck_copy(spg_problem* P, char* ws, const VjpLayout& L, int c, bool save) {
+  const size_t n4 = align_up((size_t)P->d.nvox * 4);
+  const size_t n2 = P->comp ? align_up((size_t)P->d.nvox * 2) : 0;
+  char* base = ws + L.ck + (size_t)c * L.ck_slot;
+  const int slots[2] = {save ? P->cur : 0, save ? P->old : 1};
+  for (int k = 0; k < 2; ++k) {
+    char* hi = base + k * (n4 + n2);
+    char* lo = hi + n4;
+    if (save) {
+      SPG_CK(P, hipMemcpyAsync(hi, P->xhi(slots[k]), (size_t)P->d.nvox * 4, hipMemcpyDeviceToDevice, P->stream));
+      if (P->comp)
+        SPG_CK(P, hipMemcpyAsync(lo, P->xlo(slots[k]), (size_t)P->d.nvox * 2, hipMemcpyDeviceToDevice, P->stream));
+    } else {
+      SPG_CK(P, hipMemcpyAsync(P->xhi(slots[k]), hi, (size_t)P->d.nvox * 4, hipMemcpyDeviceToDevice, P->stream));
+      if (P->comp)
+        SPG_CK(P, hipMemcpyAsync(P->xlo(slots[k]), lo, (size_t)P->d.nvox * 2, hipMemcpyDeviceToDevice, P->stream));
+    }
+  }
+  if (!save) {
+    P->cur = 0;
+    P->old = 1;
+    P->primed = false;
+  }
+  return SPG_OK;
+}
+
+// FISTA state (t_j, m_j) at iteration index j (1-based) after a restart.
+void momentum_at(const spg_problem* P, int j, double* t, double* m) {
+  double tt = 1.0, mm = 0.0;
+  for (int q = 1; q < j; ++q) {
+    const double tn = P->prm.accel ? 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tt * tt)) : 1.0;
+    mm = P->prm.accel ? (tt - 1.0) / tn : 0.0;
+    tt = tn;
+  }
+  *t = tt;
+  *m = mm;
+}
+
+// Data-term Hessian applied to a real map: A^H(w~ A in) through the x, y, z passes.
+spg_status hessian_data(spg_problem* P, const float* in, float* out) {
+  const Dims& d = P->d;
+  hipStream_t st = P->stream;
+  SPG_CK(P, launch_r2c_x(d, in, false, P->S(), P->at<float2>(P->lay.tw_m), P->at<float2>(P->lay.tw_n), st));
+  SPG_CK(P, launch_fft_cols(d, P->S(), 1, 0, P->at<float2>(P->lay.tw_y), nullptr, nullptr, nullptr, st, nullptr));
+  SPG_CK(P, launch_fft_cols(d, P->S(), 2, 4, P->at<float2>(P->lay.tw_z), P->at<float>(P->lay.ws), nullptr, nullptr,
+                            st, nullptr));
+  SPG_CK(P, launch_dc_nyquist(d, P->S(), P->at<float2>(P->lay.tw_z), P->at<float>(P->lay.w0p),
+                              P->at<float>(P->lay.wnyq), nullptr, nullptr, nullptr, st, nullptr));
+  SPG_CK(P, launch_fft_cols(d, P->S(), 1, 1, P->at<float2>(P->lay.tw_y), nullptr, nullptr, nullptr, st, nullptr));
+  SPG_CK(P, launch_c2r_x(d, P->S(), out, false, P->at<float2>(P->lay.tw_m), P->at<float2>(P->lay.tw_n), st));
+  return SPG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+spg_status spg_vjp_workspace_size(const spg_problem* P, int32_t K, int32_t C, size_t* bytes) {
+  if (!P || !bytes || K < 1 || C < 1 || C > K) return SPG_E_INVAL;
+  *bytes = vjp_layout(P, K, C).total;
+  return SPG_OK;
+}
+
+spg_status spg_run_checkpointed(spg_problem* P, int32_t K, int32_t C, void* d_vjp_ws, size_t bytes) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if (K < 1 || C < 1 || C > K) return set_err(P, SPG_E_INVAL, "need K >= 1 and 1 <= C <= K");
+  if (!P->data_set) return set_err(P, SPG_E_STATE, "spg_set_data has not succeeded");
+  if (P->store == ST_BF16) return set_err(P, SPG_E_UNSUPPORTED, "the reverse pass needs an fp32 map buffer");
+  if (!(P->L > 0)) return set_err(P, SPG_E_STATE, "L = 0");
+  if (!d_vjp_ws || (reinterpret_cast<uintptr_t>(d_vjp_ws) % kAlign) != 0)
+    return set_err(P, SPG_E_INVAL, "reverse-pass workspace must be 256-byte aligned device memory");
+  const VjpLayout L = vjp_layout(P, K, C);
+  if (bytes < L.total) return set_err(P, SPG_E_NOMEM, "reverse-pass workspace too small");
+  char* ws = reinterpret_cast<char*>(d_vjp_ws);
+  restart(P);
+  P->old = P->cur;  // x_{-1} = x_0
+  if ((s = ck_copy(P, ws, L, 0, true))) return s;
+  P->old = (P->cur + 1) % 3;
+  P->vjp_m.assign(K, 0.0);
+  for (int it = 0; it < K; ++it) {
+    if (it > 0 && it % C == 0)
+      if ((s = ck_copy(P, ws, L, it / C, true))) return s;
+    P->vjp_m[it] = P->m_cur;
+    if ((s = iterate_once(P, nullptr))) return s;
+  }
+  if ((s = ck_copy(P, ws, L, L.nseg, true))) return s;
+  P->vjp_valid = true;
+  P->vjp_K = K;
+  P->vjp_C = C;
+  P->vjp_lr = P->lr;
+  return SPG_OK;
+}
+
+spg_status spg_vjp(spg_problem* P, void* d_vjp_ws, size_t bytes, const float* d_w, const float* d_xbar,
+                   float* d_bbar, double* lam_bar, double* mu_bar) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if (!P->vjp_valid || P->lr != P->vjp_lr)
+    return set_err(P, SPG_E_STATE, "no unrolled solve recorded (spg_run_checkpointed) for these parameters");
+  if (!d_w || !d_xbar || !d_bbar || !d_vjp_ws) return set_err(P, SPG_E_INVAL, "NULL pointer");
+  const int K = P->vjp_K, C = P->vjp_C;
+  const VjpLayout L = vjp_layout(P, K, C);
+  if (bytes < L.total) return set_err(P, SPG_E_NOMEM, "reverse-pass workspace too small");
+  const Dims& d = P->d;
+  hipStream_t st = P->stream;
+  char* ws = reinterpret_cast<char*>(d_vjp_ws);
+  const size_t n4 = align_up((size_t)d.nvox * 4);
+  auto segx = [&](int i) { return reinterpret_cast<float*>(ws + L.seg_x + (size_t)i * n4); };
+  auto segg = [&](int i) { return reinterpret_cast<float*>(ws + L.seg_g + (size_t)i * n4); };
+  auto abar = [&](int k) { return reinterpret_cast<float*>(ws + L.abar + (size_t)(((k % 3) + 3) % 3) * n4); };
+  float* zbar = reinterpret_cast<float*>(ws + L.zbar);
+  float* hz = reinterpret_cast<float*>(ws + L.hz);
+  float* rbar = reinterpret_cast<float*>(ws + L.rbar);
+  double* part = reinterpret_cast<double*>(ws + L.part);
+  double* res = reinterpret_cast<double*>(ws + L.res);
+  const float* u = P->unif_u ? nullptr : P->at<float>(P->lay.u);
+  const float* v = P->unif_v ? nullptr : P->at<float>(P->lay.v);
+  const double lr = P->lr;
+
+  SPG_CK(P, launch_fill(rbar, d.nvox, 0.0f, st));
+  SPG_CK(P, hipMemcpyAsync(abar(K), d_xbar, (size_t)d.nvox * 4, hipMemcpyDeviceToDevice, st));
+  SPG_CK(P, launch_fill(abar(K - 1), d.nvox, 0.0f, st));
+  double lamb = 0, mub = 0, lrb = 0;
+  for (int sgm = L.nseg - 1; sgm >= 0; --sgm) {
+    const int j0 = sgm * C;
+    const int len = std::min(C, K - j0);
+    // replay the segment from its checkpoint, keeping x_k and the data gradient of y_k
+    if ((s = ck_copy(P, ws, L, sgm, false))) return s;
+    momentum_at(P, j0 + 1, &P->t, &P->m_cur);
+    P->j = j0 + 1;
+    SPG_CK(P, launch_get_map(d, P->xhi(P->old), P->xlo(P->old), segx(0), P->comp, st));
+    SPG_CK(P, launch_get_map(d, P->xhi(P->cur), P->xlo(P->cur), segx(1), P->comp, st));
+    for (int i = 0; i < len; ++i) {
+      if ((s = iterate_once(P, segg(i)))) return s;
+      SPG_CK(P, launch_get_map(d, P->xhi(P->cur), P->xlo(P->cur), segx(i + 2), P->comp, st));
+    }
+    // reverse through the segment
+    for (int i = len - 1; i >= 0; --i) {
+      const int k = j0 + i;
+      SPG_CK(P, launch_adj_prox(d, segx(i + 2), abar(k + 1), segg(i), u, (float)lr, zbar, rbar, part, kStatBlocks, st));
+      if ((s = hessian_data(P, zbar, hz))) return s;
+      SPG_CK(P, launch_adj_tv(d, segx(i + 1), segx(i), (float)P->vjp_m[k], zbar, hz, v, (float)lr,
+                              (float)P->prm.mu, (float)P->prm.eps, abar(k), k >= 1 ? abar(k - 1) : nullptr,
+                              part + 2 * kStatBlocks, kStatBlocks, st));
+      const int ops[3] = {RED_OP_SUM, RED_OP_SUM, RED_OP_SUM};
+      SPG_CK(P, launch_reduce(part, kStatBlocks, 3, ops, res, st));
+      double r[3];
+      if ((s = read_results_to(P, res, r, 3))) return s;
+      lamb += lr * r[0];
+      lrb += P->prm.lambda * r[0] - r[1] - P->prm.mu * r[2];
+      mub += -lr * r[2];
+    }
+  }
+  // lr = 1/L(mu): d lr / d mu = -lr^2 max(v) ||D||^2 / eps
+  mub += lrb * (-lr * lr * P->vmax * P->dn2 / P->prm.eps);
+  // b-bar = w * A(rbar)
+  SPG_CK(P, launch_r2c_x(d, rbar, false, P->S(), P->at<float2>(P->lay.tw_m), P->at<float2>(P->lay.tw_n), st));
+  SPG_CK(P, launch_fft_cols(d, P->S(), 1, 0, P->at<float2>(P->lay.tw_y), nullptr, nullptr, nullptr, st, nullptr));
+  SPG_CK(P, launch_fft_cols(d, P->S(), 2, 0, P->at<float2>(P->lay.tw_z), nullptr, nullptr, nullptr, st, nullptr));
+  SPG_CK(P, launch_expand_bbar(d, P->S(), d_w, reinterpret_cast<float2*>(d_bbar), st));
+  // back to the end state of the unrolled solve
+  if ((s = ck_copy(P, ws, L, L.nseg, false))) return s;
+  momentum_at(P, K + 1, &P->t, &P->m_cur);
+  P->j = K + 1;
+  SPG_CK(P, hipStreamSynchronize(st));
+  if (lam_bar) *lam_bar = lamb;
+  if (mu_bar) *mu_bar = mub;
+  return SPG_OK;
+}
+
+}  // extern "C"
 
 // ---------------------------------------------------------------- checkpoints
 

@@ -84,5 +84,13 @@ hipError_t launch_f32_to_bf16(const float* src, uint16_t* dst, long long n, hipS
 hipError_t launch_bf16_to_f32(const uint16_t* src, float* dst, long long n, hipStream_t st);
 hipError_t launch_fill(float* dst, long long n, float value, hipStream_t st);
 hipError_t launch_reduce(const double* partials, int n, int nq, const int* ops, double* out, hipStream_t st);
+hipError_t launch_adj_prox(const Dims& d, const float* xn, const float* abar, const float* gdat, const float* u,
+                           float lr, float* zbar, float* rbar, double* partials, int nblocks, hipStream_t st);
+hipError_t launch_adj_tv(const Dims& d, const float* xk, const float* xkm, float m, const float* zbar, const float* hz,
+                         const float* v, float lr, float mu, float eps, float* abar_k, float* abar_km,
+                         double* partials, int nblocks, hipStream_t st);
+hipError_t launch_expand_bbar(const Dims& d, const float2* S, const float* w, float2* out, hipStream_t st);
+hipError_t launch_fsc_shells(const Dims& d, const float2* S1, const float2* S2, int nshells, double* partials,
+                             int nblocks, double* out, hipStream_t st);
 
 }  // namespace spg

@@ -327,7 +327,8 @@ __device__ double block_reduce(double v, double* sh) {
 // ---------------------------------------------------------------- column FFT passes
 // Tile: NT consecutive kx columns (<= 16, one 128-byte row segment) by the whole axis.
 // mode 0: forward; mode 1: inverse; mode 2: forward, G = ws*Y - cs, inverse (z axis);
-// mode 3: as 2 and also writes per-block partials of 1/2 ws |Y|^2 - Re(conj(cs) Y)
+// mode 3: as 2 and also writes per-block partials of 1/2 ws |Y|^2 - Re(conj(cs) Y);
+// mode 4: forward, G = ws*Y, inverse (the data-term Hessian applied to a map)
 // (multiplicity 2 for 0 < kx < nx/2; the kx = 0 column is done by k_dc_nyquist).
 
 template <int L, int MODE>
@@ -375,7 +376,7 @@ __global__ void __launch_bounds__(512) k_fft_cols(float2* __restrict__ S, int P,
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       wv[i] = valid ? wsb[off0 + i * step] : 0.f;
-      cv[i] = valid ? csb[off0 + i * step] : make_float2(0.f, 0.f);
+      cv[i] = (valid && MODE != 4) ? csb[off0 + i * step] : make_float2(0.f, 0.f);
     }
     reg_stages<L, T, 1, false>(a, re, im, NT, q, s_tw);
   } else {
@@ -383,7 +384,7 @@ __global__ void __launch_bounds__(512) k_fft_cols(float2* __restrict__ S, int P,
 #pragma unroll
       for (int i = 0; i < E; ++i) {
         wv[i] = valid ? ws[ub + off0 + i * step] : 0.f;
-        cv[i] = valid ? cs[ub + off0 + i * step] : make_float2(0.f, 0.f);
+        cv[i] = (valid && MODE != 4) ? cs[ub + off0 + i * step] : make_float2(0.f, 0.f);
       }
     }
     fft_reg<L, MODE == 1, T>(a, re, im, NT, q, s_tw);
@@ -462,7 +463,8 @@ __global__ void __launch_bounds__(256) k_dc_nyquist(float2* __restrict__ S, int 
       const float2 B = make_float2(dd.y, -dd.x);
       const long long offn = (long long)myky * L + kz;
       const float w0 = w0p[offn], wn = wnyq[offn];
-      const float2 c0 = c0p[offn], cn = cnyq[offn];
+      const float2 c0 = c0p ? c0p[offn] : make_float2(0.f, 0.f);
+      const float2 cn = cnyq ? cnyq[offn] : make_float2(0.f, 0.f);
       if constexpr (OBJ) {
         if (c == 0 || ky != kyp)
           acc += 0.5 * (double)w0 * ((double)A.x * A.x + (double)A.y * A.y) - ((double)c0.x * A.x + (double)c0.y * A.y) +
@@ -1087,6 +1089,192 @@ __global__ void __launch_bounds__(256) k_reweight(Dims d, const float* __restric
   if (threadIdx.x == 0) partials[blockIdx.x] = r;
 }
 
+// ---------------------------------------------------------------- Fourier shell correlation
+// Shell sums of eq 30 over the packed half spectra of two real maps: Re F conj G, |F|^2,
+// |G|^2 per shell, with multiplicity 2 for 0 < kx < nx/2.  The packed slot 0 is split
+// into its kx = 0 and kx = nx/2 planes with the partner at (-ky, -kz).  Shell of signed
+// frequency k: floor(min(n) sqrt(sum_a (k_a / n_a)^2) + 1/2).  Per-block histograms in
+// LDS (fp64 atomics), written as block partials.
+__device__ __forceinline__ int fsc_shell(int kz, int ky, int kx, const Dims& d) {
+  const int nmin = min(d.nx, min(d.ny, d.nz));
+  const int sz = kz < d.nz / 2 ? kz : kz - d.nz;
+  const int sy = ky < d.ny / 2 ? ky : ky - d.ny;
+  const int sx = kx < d.nx / 2 ? kx : kx - d.nx;
+  const double fz = (double)sz * nmin / d.nz, fy = (double)sy * nmin / d.ny, fx = (double)sx * nmin / d.nx;
+  return (int)floor(sqrt(fz * fz + fy * fy + fx * fx) + 0.5);
+}
+
+__global__ void __launch_bounds__(256) k_fsc_shells(Dims d, const float2* __restrict__ S1,
+                                                    const float2* __restrict__ S2, int nshells,
+                                                    double* __restrict__ partials) {
+  extern __shared__ double sh[];  // 3 * nshells
+  for (int i = threadIdx.x; i < 3 * nshells; i += blockDim.x) sh[i] = 0.0;
+  __syncthreads();
+  auto acc = [&](int shell, double w, float2 f, float2 g) {
+    if (shell < nshells) {
+      atomicAdd(&sh[shell], w * ((double)f.x * g.x + (double)f.y * g.y));
+      atomicAdd(&sh[nshells + shell], w * ((double)f.x * f.x + (double)f.y * f.y));
+      atomicAdd(&sh[2 * nshells + shell], w * ((double)g.x * g.x + (double)g.y * g.y));
+    }
+  };
+  const int P = d.P;
+  const long long nh = (long long)d.nz * d.ny * P;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nh; t += (long long)gridDim.x * blockDim.x) {
+    const int kx = (int)(t % P);
+    const long long r = t / P;
+    const int ky = (int)(r % d.ny);
+    const int kz = (int)(r / d.ny);
+    const float2 f = S1[t], g = S2[t];
+    if (kx > 0) {
+      acc(fsc_shell(kz, ky, kx, d), 2.0, f, g);
+    } else {
+      const long long tp = ((long long)((d.nz - kz) & (d.nz - 1)) * d.ny + ((d.ny - ky) & (d.ny - 1))) * P;
+      const float2 fp = S1[tp], gp = S2[tp];
+      const float2 f0 = make_float2(0.5f * (f.x + fp.x), 0.5f * (f.y - fp.y));
+      const float2 fn = make_float2(0.5f * (f.y + fp.y), -0.5f * (f.x - fp.x));
+      const float2 g0 = make_float2(0.5f * (g.x + gp.x), 0.5f * (g.y - gp.y));
+      const float2 gn = make_float2(0.5f * (g.y + gp.y), -0.5f * (g.x - gp.x));
+      acc(fsc_shell(kz, ky, 0, d), 1.0, f0, g0);
+      acc(fsc_shell(kz, ky, d.nx / 2, d), 1.0, fn, gn);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 3 * nshells; i += blockDim.x)
+    partials[(long long)blockIdx.x * 3 * nshells + i] = sh[i];
+}
+
+// Fixed-order sum of the block histograms: out[q * nshells + s], q = 0..2.
+__global__ void k_fsc_final(const double* __restrict__ partials, int nblocks, int nshells, double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 3 * nshells) return;
+  double acc = 0.0;
+  for (int b = 0; b < nblocks; ++b) acc += partials[(long long)b * 3 * nshells + i];
+  out[i] = acc;
+}
+
+// ---------------------------------------------------------------- adjoint of unrolled SPG
+// Reverse step k of x_{k+1} = soft(z_k, lr lam u), z_k = y_k - lr (g_data(y_k) + mu g_tv(y_k)),
+// y_k = x_k + m_k (x_k - x_{k-1}) (chain rule; a.e. derivatives at the kinks).
+
+// zbar = [x_{k+1} != 0] abar_{k+1};  rbar += lr zbar;  partials: sum tbar u with
+// tbar = -sign(x_{k+1}) zbar (threshold adjoint), and sum zbar g_data(y_k).
+__global__ void __launch_bounds__(256) k_adj_prox(long long n, const float* __restrict__ xn,
+                                                  const float* __restrict__ abar, const float* __restrict__ gdat,
+                                                  const float* __restrict__ u, float lr, float* __restrict__ zbar,
+                                                  float* __restrict__ rbar, double* __restrict__ partials) {
+  __shared__ double s_red[8];
+  double s_t = 0.0, s_g = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const float x = xn[i];
+    const float zb = x != 0.f ? abar[i] : 0.f;
+    zbar[i] = zb;
+    rbar[i] += lr * zb;
+    const float uu = u ? u[i] : 1.0f;
+    s_t += -(double)copysignf(1.0f, x) * (x != 0.f ? (double)zb : 0.0) * uu;
+    s_g += (double)zb * gdat[i];
+  }
+  const int nb = gridDim.x;
+  double r = block_reduce<RED_OP_SUM>(s_t, s_red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+  r = block_reduce<RED_OP_SUM>(s_g, s_red);
+  if (threadIdx.x == 0) partials[nb + blockIdx.x] = r;
+}
+
+// Weighted dual and its Hessian product at one point j from the three backward differences
+// d = (Dy)_j, e = (D zbar)_j:  p = v d / max(eps, |d|),  q = v J(d) e,
+// J = I / eps for |d| < eps, (I - d d^T / |d|^2) / |d| otherwise.
+__device__ __forceinline__ void adj_dual(const float d[3], const float e[3], float vv, float eps, float p[3],
+                                         float q[3]) {
+  const float n2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  const float n = sqrtf(n2);
+  if (n < eps) {
+    const float s = vv / eps;
+    for (int a = 0; a < 3; ++a) {
+      p[a] = s * d[a];
+      q[a] = s * e[a];
+    }
+  } else {
+    const float de = d[0] * e[0] + d[1] * e[1] + d[2] * e[2];
+    const float s = vv / n;
+    for (int a = 0; a < 3; ++a) {
+      p[a] = s * d[a];
+      q[a] = s * (e[a] - d[a] * de / n2);
+    }
+  }
+}
+
+// ybar = zbar - lr (hz + mu H_tv(y_k) zbar); abar_k += (1 + m) ybar; abar_{k-1} = -m ybar
+// (first contribution); partial: sum zbar g_tv(y_k).  y_k from the stored fp32 maps.
+// One thread per voxel, neighbours read through the cache (the reverse pass is not the
+// hot path).
+__global__ void __launch_bounds__(256) k_adj_tv(Dims dm, const float* __restrict__ xk, const float* __restrict__ xkm,
+                                                float m, const float* __restrict__ zbar, const float* __restrict__ hz,
+                                                const float* __restrict__ v, float lr, float mu, float eps,
+                                                float* __restrict__ abar_k, float* __restrict__ abar_km,
+                                                double* __restrict__ partials) {
+  __shared__ double s_red[8];
+  const int nx = dm.nx, ny = dm.ny, nz = dm.nz;
+  const long long plane = (long long)nx * ny;
+  auto idx = [&](int z, int y, int x) { return (long long)(z & (nz - 1)) * plane + (long long)(y & (ny - 1)) * nx + (x & (nx - 1)); };
+  auto Y = [&](long long i) { return xk[i] + m * (xk[i] - xkm[i]); };
+  auto point = [&](int z, int y, int x, float p[3], float q[3]) {
+    const long long i = idx(z, y, x);
+    const long long iz = idx(z - 1, y, x), iy = idx(z, y - 1, x), ix = idx(z, y, x - 1);
+    const float yc = Y(i), zc = zbar[i];
+    const float d[3] = {yc - Y(iz), yc - Y(iy), yc - Y(ix)};
+    const float e[3] = {zc - zbar[iz], zc - zbar[iy], zc - zbar[ix]};
+    adj_dual(d, e, v ? v[i] : 1.0f, eps, p, q);
+  };
+  double s_tv = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < dm.nvox;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / plane);
+    float p0[3], q0[3], pz[3], qz[3], py[3], qy[3], px[3], qx[3];
+    point(z, y, x, p0, q0);
+    point(z + 1, y, x, pz, qz);
+    point(z, y + 1, x, py, qy);
+    point(z, y, x + 1, px, qx);
+    const float gtv = (p0[0] - pz[0]) + (p0[1] - py[1]) + (p0[2] - px[2]);
+    const float htv = (q0[0] - qz[0]) + (q0[1] - qy[1]) + (q0[2] - qx[2]);
+    const float zb = zbar[i];
+    s_tv += (double)zb * gtv;
+    const float yb = zb - lr * (hz[i] + mu * htv);
+    abar_k[i] += (1.0f + m) * yb;
+    if (abar_km) abar_km[i] = -m * yb;
+  }
+  double r = block_reduce<RED_OP_SUM>(s_tv, s_red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+// Full complex b-bar = w * A(rbar) / (unitary A) from the packed half spectrum of rbar
+// (after the x, y, z forward passes), interleaved re/im, FFT order.
+__global__ void __launch_bounds__(256) k_expand_bbar(Dims d, const float2* __restrict__ S, const float* __restrict__ w,
+                                                     float2* __restrict__ out) {
+  const int P = d.P;
+  const float sc = (float)(1.0 / sqrt((double)d.nvox));
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < d.nvox;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int kx = (int)(i % d.nx);
+    const int ky = (int)((i / d.nx) % d.ny);
+    const int kz = (int)(i / ((long long)d.nx * d.ny));
+    const int nky = (d.ny - ky) & (d.ny - 1), nkz = (d.nz - kz) & (d.nz - 1);
+    float2 val;
+    if (kx == 0 || kx == P) {
+      const float2 z1 = S[((long long)kz * d.ny + ky) * P];
+      const float2 z2 = S[((long long)nkz * d.ny + nky) * P];
+      val = kx == 0 ? make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y))
+                    : make_float2(0.5f * (z1.y + z2.y), -0.5f * (z1.x - z2.x));
+    } else if (kx < P) {
+      val = S[((long long)kz * d.ny + ky) * P + kx];
+    } else {
+      const float2 t = S[((long long)nkz * d.ny + nky) * P + (d.nx - kx)];
+      val = make_float2(t.x, -t.y);
+    }
+    const float ww = w[i] * sc;
+    out[i] = make_float2(ww * val.x, ww * val.y);
+  }
+}
+
 struct RedOps {
   int op[8];
 };
@@ -1162,6 +1350,7 @@ hipError_t launch_fft_cols(const Dims& d, float2* S, int axis, int mode, const f
     case 1: SPG_DISPATCH_L(L, SPG_COLS(1)); break;
     case 2: SPG_DISPATCH_L(L, SPG_COLS(2)); break;
     case 3: SPG_DISPATCH_L(L, SPG_COLS(3)); break;
+    case 4: SPG_DISPATCH_L(L, SPG_COLS(4)); break;
     default: return hipErrorInvalidValue;
   }
 #undef SPG_COLS
@@ -1312,6 +1501,33 @@ hipError_t launch_reduce(const double* partials, int n, int nq, const int* ops, 
   RedOps r{};
   for (int i = 0; i < nq; ++i) r.op[i] = ops[i];
   k_reduce<<<1, 256, 0, st>>>(partials, n, nq, r, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fsc_shells(const Dims& d, const float2* S1, const float2* S2, int nshells, double* partials,
+                             int nblocks, double* out, hipStream_t st) {
+  k_fsc_shells<<<nblocks, 256, 3 * nshells * sizeof(double), st>>>(d, S1, S2, nshells, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_fsc_final<<<(3 * nshells + 255) / 256, 256, 0, st>>>(partials, nblocks, nshells, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_prox(const Dims& d, const float* xn, const float* abar, const float* gdat, const float* u,
+                           float lr, float* zbar, float* rbar, double* partials, int nblocks, hipStream_t st) {
+  k_adj_prox<<<nblocks, 256, 0, st>>>(d.nvox, xn, abar, gdat, u, lr, zbar, rbar, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_tv(const Dims& d, const float* xk, const float* xkm, float m, const float* zbar, const float* hz,
+                         const float* v, float lr, float mu, float eps, float* abar_k, float* abar_km,
+                         double* partials, int nblocks, hipStream_t st) {
+  k_adj_tv<<<nblocks, 256, 0, st>>>(d, xk, xkm, m, zbar, hz, v, lr, mu, eps, abar_k, abar_km, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_bbar(const Dims& d, const float2* S, const float* w, float2* out, hipStream_t st) {
+  k_expand_bbar<<<ew_grid(d.nvox), 256, 0, st>>>(d, S, w, out);
   return hipGetLastError();
 }
 

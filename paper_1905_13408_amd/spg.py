@@ -72,6 +72,11 @@ def lib() -> ctypes.CDLL:
         "spg_set_state": [P, P, c_size_t],
         "spg_profile_begin": [P, c_int32, c_int32],
         "spg_profile_end": [P, POINTER(c_double), POINTER(c_int32)],
+        "spg_vjp_workspace_size": [P, c_int32, c_int32, POINTER(c_size_t)],
+        "spg_run_checkpointed": [P, c_int32, c_int32, P, c_size_t],
+        "spg_vjp": [P, P, c_size_t, P, P, P, POINTER(c_double), POINTER(c_double)],
+        "spg_fsc_workspace_size": [c_int32, c_int32, c_int32, c_int32, POINTER(c_size_t)],
+        "spg_fsc": [c_int32, c_int32, c_int32, P, P, c_int32, P, c_size_t, P, POINTER(c_double)],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
@@ -246,6 +251,29 @@ class SPGSolver:
         self._check(self._L.spg_profile_end(self._h, ms, n))
         return {k: (ms[i], n[i]) for i, k in enumerate(KERNELS)}
 
+    # ------------------------------------------------------------------ reverse mode
+    def run_checkpointed(self, K: int, C: int):
+        """Restart at the current map and run K iterations, checkpointing every C."""
+        n = c_size_t(0)
+        self._check(self._L.spg_vjp_workspace_size(self._h, int(K), int(C), byref(n)))
+        if getattr(self, "_vjp_raw", None) is None or self._vjp_bytes < n.value:
+            self._vjp_raw = self.torch.empty(n.value + 256, dtype=self.torch.uint8, device=self.device)
+            self._vjp_bytes = int(n.value)
+        off = (-self._vjp_raw.data_ptr()) % 256
+        self._vjp_ptr = c_void_p(self._vjp_raw.data_ptr() + off)
+        self._check(self._L.spg_run_checkpointed(self._h, int(K), int(C), self._vjp_ptr, c_size_t(self._vjp_bytes)))
+
+    def vjp(self, w, xbar):
+        """(lam_bar, mu_bar, b_bar) for dloss/dx_K = xbar after run_checkpointed."""
+        torch = self.torch
+        w = self._dev(w, torch.float32)
+        xbar = self._dev(xbar, torch.float32)
+        bbar = torch.empty(self.shape, dtype=torch.complex64, device=self.device)
+        lb, mb = c_double(), c_double()
+        self._check(self._L.spg_vjp(self._h, self._vjp_ptr, c_size_t(self._vjp_bytes), _ptr(w), _ptr(xbar),
+                                    _ptr(torch.view_as_real(bbar)), byref(lb), byref(mb)))
+        return lb.value, mb.value, bbar
+
     @property
     def handle(self):
         return self._h
@@ -273,3 +301,31 @@ def solve(vol_w, vol_b, shape, lam, mu, eps, rounds, iters, eps1, eps2, accel=Tr
             s.reweight(eps1, eps2)
         s.run(iters)
     return s
+
+
+def fsc(map1, map2, nshells=None, stream=None):
+    """Gold-standard FSC of eq 30 between two float32 device maps of the same (nz, ny, nx) shape."""
+    import numpy as np
+    import torch
+
+    if map1.shape != map2.shape or map1.dim() != 3:
+        raise ValueError("maps must be 3D and of the same shape")
+    nz, ny, nx = (int(s) for s in map1.shape)
+    if nshells is None:
+        nshells = min(nx, ny, nz) // 2 + 1
+    m1 = map1.to(torch.float32).contiguous()
+    m2 = map2.to(torch.float32).contiguous()
+    L = lib()
+    n = c_size_t(0)
+    st = L.spg_fsc_workspace_size(nx, ny, nz, int(nshells), byref(n))
+    if st != SPG_OK:
+        raise SPGError(st, L.spg_status_string(st).decode())
+    raw = torch.empty(n.value + 256, dtype=torch.uint8, device=m1.device)
+    off = (-raw.data_ptr()) % 256
+    stream = stream if stream is not None else torch.cuda.current_stream(m1.device)
+    out = (c_double * int(nshells))()
+    st = L.spg_fsc(nx, ny, nz, _ptr(m1), _ptr(m2), int(nshells), c_void_p(raw.data_ptr() + off), n,
+                   c_void_p(stream.cuda_stream), out)
+    if st != SPG_OK:
+        raise SPGError(st, L.spg_status_string(st).decode())
+    return np.array(out[:], dtype=np.float64)

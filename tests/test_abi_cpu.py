@@ -105,3 +105,13 @@ def test_null_handles_are_rejected(L):
     assert L.spg_reweight(None, 0.1, 0.1) == -1
     assert L.spg_final_check(None, None, None, None) == -1
     assert b"NULL" in L.spg_last_error(None)
+
+
+def test_fsc_argument_validation(L):
+    n = ctypes.c_size_t()
+    assert L.spg_fsc_workspace_size(6, 8, 8, 5, ctypes.byref(n)) == -1
+    assert L.spg_fsc_workspace_size(8, 8, 8, 0, ctypes.byref(n)) == -1
+    assert L.spg_fsc_workspace_size(8, 8, 8, 2000, ctypes.byref(n)) == -1
+    assert L.spg_fsc_workspace_size(8, 8, 8, 5, ctypes.byref(n)) == 0 and n.value > 2 * 8 * 8 * 4 * 8
+    out = (ctypes.c_double * 5)()
+    assert L.spg_fsc(8, 8, 8, None, None, 5, None, 0, None, out) == -1

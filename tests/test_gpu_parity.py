@@ -333,3 +333,115 @@ def test_bf16_storage_weighted_ragged_and_deterministic():
     err = rel_l2(to_np(outs[0]), O.spg_solve(p, 25, x0=x0.astype(np.float64)))
     print(f"bf16 weighted rel L2 = {err:.3e}", flush=True)
     assert err < BF16_TOL
+
+
+# ------------------------------------------------------------------ gold-standard FSC (eq 30)
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (16, 64, 32), (128, 128, 128)])
+def test_fsc_matches_oracle(shape):
+    from oracle import fsc_ref as FR
+
+    announce(f"FSC shape={shape}")
+    vol = synth.make_volume(shape, 40, 2, 1.2, 0.3 * min(shape), 0.5, seed=5, config_id=30)
+    rng = np.random.default_rng(np.random.SeedSequence([31, *shape]))
+    a = vol.x_true + (rng.standard_normal(shape) * 0.3).astype(np.float32)
+    b = vol.x_true + (rng.standard_normal(shape) * 0.3).astype(np.float32)
+    nsh = min(shape) // 2 + 1
+    got = spg.fsc(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), nsh)
+    ref = FR.fsc(a.astype(np.float64), b.astype(np.float64), nsh)
+    print("fsc max abs diff", float(np.max(np.abs(got - ref))), flush=True)
+    assert np.max(np.abs(got - ref)) < 1e-5
+    same = spg.fsc(torch.from_numpy(a).cuda(), torch.from_numpy(a).cuda(), nsh)
+    assert np.max(np.abs(same - 1.0)) < 1e-6
+
+
+# ------------------------------------------------------------------ reverse mode (adjoint)
+
+def _adj_setup(shape, seed):
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 777]))
+    w = synth.fourier_weights(shape).astype(np.float32)
+    vol = synth.make_volume(shape, max(4, int(np.prod(shape) // 2000)), 2, 1.2, 0.3 * min(shape), 0.5, seed=seed,
+                            config_id=50)
+    return vol.w, vol.b, vol.x_true, rng
+
+
+@pytest.mark.parametrize("shape,K,C", [((16, 32, 32), 20, 7), ((32, 32, 32), 12, 12)])
+def test_vjp_matches_fp64_reference_gradient(shape, K, C):
+    from oracle import adjoint_ref as A
+
+    announce(f"vjp vs FP64 reference shape={shape} K={K} C={C}")
+    w, b, xt, _ = _adj_setup(shape, 41)
+    lam, mu, eps = 0.01, 0.05, 1e-2
+    s = spg.SPGSolver(shape, lam, mu, eps)
+    s.set_data(w, b)
+    s.set_map(None)
+    s.run_checkpointed(K, C)
+    xK = s.get_map()
+    xbar = 2.0 * (xK - torch.from_numpy(xt).cuda())
+    lb, mb, bb = s.vjp(w, xbar)
+    p = oracle_problem(w, b, lam, mu, eps)
+    loss, olb, omb, obb = A.loss_and_grad(p, K, xt.astype(np.float64))
+    eb = rel_l2(bb.cpu().numpy().view(np.float32).astype(np.float64),
+                obb.astype(np.complex128).view(np.float64))
+    print(f"lam_bar {lb:.6e} vs {olb:.6e}; mu_bar {mb:.6e} vs {omb:.6e}; b_bar rel L2 {eb:.3e}", flush=True)
+    assert abs(lb - olb) <= 1e-3 * abs(olb)
+    assert abs(mb - omb) <= 1e-3 * abs(omb)
+    assert eb < 1e-3
+    # the problem is left at x_K
+    assert torch.equal(s.get_map(), xK)
+
+
+def test_autograd_function_vs_finite_differences():
+    from paper_1905_13408_amd.autograd import UnrolledSPG
+
+    shape, K, C = (32, 32, 32), 15, 5
+    announce("autograd Function vs central differences (h = 1e-3)")
+    w, b, xt, rng = _adj_setup(shape, 43)
+    s = spg.SPGSolver(shape, 0.01, 0.05, 1e-2)
+    wt = torch.from_numpy(w).cuda()
+    xtt = torch.from_numpy(xt).cuda()
+    lam = torch.tensor(0.01, dtype=torch.float64, requires_grad=True)
+    mu = torch.tensor(0.05, dtype=torch.float64, requires_grad=True)
+    bt = torch.from_numpy(b).cuda().requires_grad_(True)
+    x = UnrolledSPG.apply(lam, mu, bt, s, wt, K, C)
+    loss = ((x - xtt) ** 2).sum()
+    loss.backward()
+
+    def L(lv, mv, bv):
+        with torch.no_grad():
+            xx = UnrolledSPG.apply(torch.tensor(lv, dtype=torch.float64), torch.tensor(mv, dtype=torch.float64), bv,
+                                   s, wt, K, C)
+            return float(((xx.double() - xtt.double()) ** 2).sum())
+
+    h = 1e-3
+    fd_l = (L(0.01 * (1 + h), 0.05, bt.detach()) - L(0.01 * (1 - h), 0.05, bt.detach())) / (2 * h * 0.01)
+    fd_m = (L(0.01, 0.05 * (1 + h), bt.detach()) - L(0.01, 0.05 * (1 - h), bt.detach())) / (2 * h * 0.05)
+    db = torch.from_numpy((rng.standard_normal(shape) + 1j * rng.standard_normal(shape)).astype(np.complex64)).cuda()
+    fd_b = (L(0.01, 0.05, bt.detach() + h * db) - L(0.01, 0.05, bt.detach() - h * db)) / (2 * h)
+    an_b = float(torch.sum(torch.real(torch.conj(bt.grad) * db)).item())
+    print(f"d/dlam {lam.grad.item():.5e} fd {fd_l:.5e}; d/dmu {mu.grad.item():.5e} fd {fd_m:.5e}; "
+          f"d/db.v {an_b:.5e} fd {fd_b:.5e}", flush=True)
+    assert abs(lam.grad.item() - fd_l) <= 2e-2 * abs(fd_l)
+    assert abs(mu.grad.item() - fd_m) <= 2e-2 * abs(fd_m)
+    assert abs(an_b - fd_b) <= 2e-2 * abs(fd_b)
+
+
+def test_differentiation_workload_128_vs_fp64_reference():
+    from oracle import adjoint_ref as A
+
+    vol, c = synth.make_config(5)
+    K, C = c["iters"], 10
+    announce(f"differentiation workload 128^3, K={K}, checkpoint every {C}")
+    s = spg.SPGSolver(c["shape"], c["lam"], c["mu"], c["eps"])
+    s.set_data(vol.w, vol.b)
+    s.set_map(None)
+    s.run_checkpointed(K, C)
+    xt = torch.from_numpy(vol.x_true).cuda()
+    lb, mb, bb = s.vjp(vol.w, 2.0 * (s.get_map() - xt))
+    p = oracle_problem(vol.w, vol.b, c["lam"], c["mu"], c["eps"])
+    loss, olb, omb, obb = A.loss_and_grad(p, K, vol.x_true.astype(np.float64))
+    eb = rel_l2(bb.cpu().numpy().view(np.float32).astype(np.float64), obb.astype(np.complex128).view(np.float64))
+    print(f"128^3: lam_bar {lb:.6e} vs {olb:.6e}; mu_bar {mb:.6e} vs {omb:.6e}; b_bar rel L2 {eb:.3e}", flush=True)
+    assert abs(lb - olb) <= 1e-3 * abs(olb)
+    assert abs(mb - omb) <= 1e-3 * abs(omb)
+    assert eb < 1e-3
