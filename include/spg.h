@@ -70,7 +70,7 @@ typedef struct spg_problem spg_problem;   /* opaque, owned by the library */
                                     arithmetic); excludes SPG_FLAG_COMPENSATED             */
 
 typedef struct {
-  int32_t nx, ny, nz;   /* grid; each a power of two in [4, 512]                        */
+  int32_t nx, ny, nz;   /* grid; each a power of two in [4, 512], or 160 or 192        */
   double lambda;        /* l1 weight (paper alpha), >= 0                                */
   double mu;            /* TV weight (paper beta), >= 0                                 */
   double eps;           /* Nesterov smoothing parameter (paper mu in eq 14), > 0        */
@@ -181,7 +181,7 @@ spg_status spg_vjp(spg_problem* P, void* d_vjp_ws, size_t bytes, const float* d_
                    float* d_bbar, double* lam_bar, double* mu_bar);
 
 /* Gold-standard Fourier shell correlation of eq 30 (section 2.3) between two real maps
- * d_map1, d_map2 (nz*ny*nx float each, each axis a power of two in [4, 512]):
+ * d_map1, d_map2 (nz*ny*nx float each, each axis as in spg_params):
  *   FSC(s) = Re sum_{k in s} F conj G / sqrt(sum_{k in s} |F|^2 sum_{k in s} |G|^2)
  * over the full spectrum, shell s = floor(min(n) sqrt(sum_a (k_a / n_a)^2) + 1/2) of the
  * signed frequency k (for a cubic grid the rounded |k|), s in [0, nshells), 1 <= nshells

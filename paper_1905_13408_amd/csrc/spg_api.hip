@@ -30,6 +30,10 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
 
+// Supported axis lengths: powers of two in [4, 512], and the mixed-radix 160 = 5 * 32 and
+// 192 = 3 * 64 (their x-axis half lengths 80 and 96 are also supported transforms).
+bool axis_ok(int n) { return pow2_in(n, 4, 512) || n == 160 || n == 192; }
+
 struct Layout {
   size_t xhi[3], xlo[3], u, v, S, rbuf, xprev, ws, w0p, wnyq, cs, c0p, cnyq, tw_m, tw_n, tw_y, tw_z, part, res, total;
 };
@@ -72,8 +76,8 @@ Layout make_layout(const spg_params& p) {
 const char* check_params(const spg_params* p, spg_status* st) {
   *st = SPG_E_INVAL;
   if (!p) return "params is NULL";
-  if (!pow2_in(p->nx, 4, 512) || !pow2_in(p->ny, 4, 512) || !pow2_in(p->nz, 4, 512))
-    return "nx, ny, nz must be powers of two in [4, 512]";
+  if (!axis_ok(p->nx) || !axis_ok(p->ny) || !axis_ok(p->nz))
+    return "nx, ny, nz must be powers of two in [4, 512], or 160 or 192";
   if (!std::isfinite(p->lambda) || p->lambda < 0) return "lambda must be finite and >= 0";
   if (!std::isfinite(p->mu) || p->mu < 0) return "mu must be finite and >= 0";
   if (!std::isfinite(p->eps) || p->eps <= 0) return "eps must be finite and > 0";
@@ -641,7 +645,7 @@ FscLayout fsc_layout(int nx, int ny, int nz, int nshells) {
 }
 
 bool fsc_args_ok(int nx, int ny, int nz, int nshells) {
-  return pow2_in(nx, 4, 512) && pow2_in(ny, 4, 512) && pow2_in(nz, 4, 512) && nshells >= 1 && nshells <= 1024;
+  return axis_ok(nx) && axis_ok(ny) && axis_ok(nz) && nshells >= 1 && nshells <= 1024;
 }
 }  // namespace
 

@@ -100,10 +100,46 @@ __device__ __forceinline__ void dft8(float2* a) {
   a[7] = csub(e[3], o3);
 }
 
+// 3-point DFT: with s = a1 + a2, d = a1 - a2, t = a0 - s/2:
+// X0 = a0 + s, X1 = t -+ i (sqrt3/2) d, X2 = t +- i (sqrt3/2) d  (upper sign forward).
+template <bool INV>
+__device__ __forceinline__ void dft3(float2* a) {
+  const float h = 0.86602540378443864676f;
+  const float2 sm = cadd(a[1], a[2]);
+  const float2 d = csub(a[1], a[2]);
+  const float2 t = make_float2(a[0].x - 0.5f * sm.x, a[0].y - 0.5f * sm.y);
+  const float2 ud = rot_mi<INV>(make_float2(h * d.x, h * d.y));  // -+ i (sqrt3/2) d
+  a[0] = cadd(a[0], sm);
+  a[1] = cadd(t, ud);
+  a[2] = csub(t, ud);
+}
+
+// 5-point DFT with b1 = a1 + a4, b2 = a2 + a3, d1 = a1 - a4, d2 = a2 - a3, c_k = cos(2 pi k/5),
+// s_k = sin(2 pi k/5): X1,4 = a0 + c1 b1 + c2 b2 -+ i (s1 d1 + s2 d2),
+// X2,3 = a0 + c2 b1 + c1 b2 -+ i (s2 d1 - s1 d2)  (upper sign forward).
+template <bool INV>
+__device__ __forceinline__ void dft5(float2* a) {
+  const float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
+  const float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;
+  const float2 b1 = cadd(a[1], a[4]), b2 = cadd(a[2], a[3]);
+  const float2 d1 = csub(a[1], a[4]), d2 = csub(a[2], a[3]);
+  const float2 r1 = make_float2(a[0].x + c1 * b1.x + c2 * b2.x, a[0].y + c1 * b1.y + c2 * b2.y);
+  const float2 r2 = make_float2(a[0].x + c2 * b1.x + c1 * b2.x, a[0].y + c2 * b1.y + c1 * b2.y);
+  const float2 q1 = rot_mi<INV>(make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y));
+  const float2 q2 = rot_mi<INV>(make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y));
+  a[0] = cadd(a[0], cadd(b1, b2));
+  a[1] = cadd(r1, q1);
+  a[4] = csub(r1, q1);
+  a[2] = cadd(r2, q2);
+  a[3] = csub(r2, q2);
+}
+
 template <int R, bool INV>
 __device__ __forceinline__ void dft(float2* a) {
   if constexpr (R == 2) dft2<INV>(a);
+  else if constexpr (R == 3) dft3<INV>(a);
   else if constexpr (R == 4) dft4<INV>(a);
+  else if constexpr (R == 5) dft5<INV>(a);
   else dft8<INV>(a);
 }
 
@@ -115,14 +151,51 @@ __device__ __forceinline__ void dft(float2* a) {
 // butterfly j reads j + r L/R, twiddles by exp(-+2 pi i r (j mod Ns) / (Ns R)), and
 // writes (j - j mod Ns) R + j mod Ns + r Ns.
 
-constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
+// Stage radices of a supported length L = 2^a 3^b 5^c (at most one 3 and one 5): for a
+// power of two, radix-8 stages and one closing radix-4 or radix-2 stage; for a mixed
+// length, the radix-5 / radix-3 stage first and then radix-4 stages (and one radix 2),
+// which keeps more threads per transform.  T (threads per transform) must divide L / R
+// of every stage; the default is the largest such value up to 16.
+struct RadixList {
+  int n;
+  int r[12];
+};
+
+constexpr RadixList make_plan(int L) {
+  RadixList p{};
+  int rest = L;
+  if (rest % 5 == 0) { p.r[p.n++] = 5; rest /= 5; }
+  if (rest % 3 == 0) { p.r[p.n++] = 3; rest /= 3; }
+  const bool mixed = rest != L;
+  if (mixed) {
+    while (rest % 4 == 0 && rest > 2) { p.r[p.n++] = 4; rest /= 4; }
+  } else {
+    while (rest % 8 == 0) { p.r[p.n++] = 8; rest /= 8; }
+    if (rest % 4 == 0) { p.r[p.n++] = 4; rest /= 4; }
+  }
+  if (rest == 2) { p.r[p.n++] = 2; rest = 1; }
+  return p;
+}
+
+constexpr int gcdc(int a, int b) { return b == 0 ? a : gcdc(b, a % b); }
+
+constexpr int plan_gcd(int L) {
+  RadixList p = make_plan(L);
+  int g = 0;
+  for (int s = 0; s < p.n; ++s) g = gcdc(g, L / p.r[s]);
+  return g;
+}
+
+constexpr int largest_divisor_le(int g, int cap) {
+  int t = cap < g ? cap : g;
+  while (t > 1 && g % t != 0) --t;
+  return t < 1 ? 1 : t;
+}
 
 template <int L>
 struct FftPlan {
-  static constexpr int lg = ilog2c(L);
-  static constexpr int n8 = lg / 3;
-  static constexpr int rem = lg % 3;
-  static constexpr int T = (L >= 8) ? ((L / 8) < 16 ? (L / 8) : 16) : 1;
+  static constexpr RadixList plan = make_plan(L);
+  static constexpr int T = largest_divisor_le(plan_gcd(L), 16);
 };
 
 template <int L, int T, int R, bool INV>
@@ -144,7 +217,7 @@ __device__ __forceinline__ void fft_stage(float* __restrict__ re, float* __restr
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = q + T * b;
-    const int k = j & (Ns - 1);
+    const int k = j % Ns;
     if (Ns > 1) {
       const int step = L / (Ns * R);
 #pragma unroll
@@ -166,20 +239,20 @@ __device__ __forceinline__ void fft_stage(float* __restrict__ re, float* __restr
   __syncthreads();
 }
 
+template <int L, int S, bool INV>
+__device__ __forceinline__ void lds_stages(float* re, float* im, int ps, int q, int Ns, const float2* tw) {
+  constexpr RadixList pl = make_plan(L);
+  if constexpr (S < pl.n) {
+    constexpr int R = pl.r[S];
+    fft_stage<L, FftPlan<L>::T, R, INV>(re, im, ps, q, Ns, tw);
+    lds_stages<L, S + 1, INV>(re, im, ps, q, Ns * R, tw);
+  }
+}
+
 template <int L, bool INV>
 __device__ __forceinline__ void fft_lds(float* re, float* im, int ps, int q, const float2* __restrict__ tw) {
-  using P = FftPlan<L>;
   __syncthreads();
-  int Ns = 1;
-  if constexpr (P::n8 > 0) {
-#pragma unroll
-    for (int s = 0; s < P::n8; ++s) {
-      fft_stage<L, P::T, 8, INV>(re, im, ps, q, Ns, tw);
-      Ns *= 8;
-    }
-  }
-  if constexpr (P::rem == 2) fft_stage<L, P::T, 4, INV>(re, im, ps, q, Ns, tw);
-  if constexpr (P::rem == 1) fft_stage<L, P::T, 2, INV>(re, im, ps, q, Ns, tw);
+  lds_stages<L, 0, INV>(re, im, ps, q, 1, tw);
 }
 
 // Register-resident variant.  Thread q of a transform owns the points q + T i,
@@ -192,15 +265,14 @@ constexpr int reg_e(int L, int T) { return L / T; }
 
 template <int L, int TT = FftPlan<L>::T>
 struct RegPlan {
-  static constexpr int n8 = FftPlan<L>::n8;
-  static constexpr int rem = FftPlan<L>::rem;
+  static constexpr RadixList plan = make_plan(L);
   static constexpr int T = TT;
   static constexpr int E = L / T;
-  static constexpr int ns = n8 + (rem ? 1 : 0);
-  static constexpr int radix(int s) { return s < n8 ? 8 : (rem == 2 ? 4 : 2); }
+  static constexpr int ns = plan.n;
+  static constexpr int radix(int s) { return plan.r[s]; }
   static constexpr int span(int s) {  // Ns before stage s
     int v = 1;
-    for (int t = 0; t < s; ++t) v *= radix(t);
+    for (int t = 0; t < s; ++t) v *= plan.r[t];
     return v;
   }
 };
@@ -233,14 +305,14 @@ __device__ __forceinline__ void reg_stage(float2 (&a)[reg_e(L, TT)], float* __re
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = q + T * b;
-    const int k = j & (Ns - 1);
+    const int k = j % Ns;
     if constexpr (Ns > 1) {
 #pragma unroll
       for (int r = 1; r < R; ++r) {
         // exp(+2 pi i m / L) = table[L - m]: the inverse reads other addresses than the
         // forward, so the compiler does not keep forward twiddles live for reuse
         const int m = r * k * (L / (Ns * R));
-        const float2 w = twl[INV ? ((L - m) & (L - 1)) : m];
+        const float2 w = twl[INV ? ((L - m) % L) : m];
         v[b][r] = cmul(v[b][r], w);
       }
     }
@@ -283,7 +355,7 @@ __device__ __forceinline__ void fft_reg(float2 (&a)[reg_e(L, TT)], float* re, fl
 // enough for two 512-thread blocks per CU.
 template <int L>
 struct ColT {
-  static constexpr int T = L >= 256 ? 32 : FftPlan<L>::T;
+  static constexpr int T = (L >= 256 && (L & (L - 1)) == 0) ? 32 : FftPlan<L>::T;
 };
 
 // ---------------------------------------------------------------- XCD-aware block order
@@ -434,7 +506,7 @@ __global__ void __launch_bounds__(256) k_dc_nyquist(float2* __restrict__ S, int 
   const int tid = threadIdx.x;
   const int c = tid & 1, q = tid >> 1;
   const int ky = blockIdx.x;
-  const int kyp = (ny - ky) & (ny - 1);
+  const int kyp = (ny - ky) % ny;
   const int myky = c == 0 ? ky : kyp;
   const long long pstride = (long long)ny * P;
   const long long base = (long long)myky * P;
@@ -455,7 +527,7 @@ __global__ void __launch_bounds__(256) k_dc_nyquist(float2* __restrict__ S, int 
   for (int i = 0; i < NE; ++i) {
     const int kz = q + T * i;
     if (kz < L) {
-      const int kzp = (L - kz) & (L - 1);
+      const int kzp = (L - kz) % L;
       const float2 z1 = make_float2(re[kz * 2], im[kz * 2]);
       const float2 z2 = make_float2(pre[kzp * 2], pim[kzp * 2]);
       const float2 A = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
@@ -700,16 +772,17 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
   const int z0 = bz * PT_ZC;
   const int z1 = min(z0 + PT_ZC, nz);
   const long long plane = (long long)nx * ny;
-  const int mx = nx - 1, my = ny - 1, mz = nz - 1;
+  // periodic wrap of a coordinate (any grid size; the offsets below are computed once per block)
+  auto wrapm = [](int v, int n) { return ((v % n) + n) % n; };
 
   // own voxels: in-plane offsets
-  const int gx = (x0 + tx) & mx;
+  const int gx = wrapm(x0 + tx, nx);
   const bool vx = (x0 + tx) < nx;
   int own_off[2];
   bool vown[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    own_off[h] = ((y0 + ty + 4 * h) & my) * nx + gx;
+    own_off[h] = wrapm(y0 + ty + 4 * h, ny) * nx + gx;
     vown[h] = vx && (y0 + ty + 4 * h) < ny;
   }
   // halo point of this thread (tid < NHALO)
@@ -719,7 +792,7 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
   else if (tid < 2 * YW) { hly = TY; hlx = tid - YW - 1; }
   else if (tid < 2 * YW + TY) { hlx = -1; hly = tid - 2 * YW; }
   else { hlx = TX; hly = tid - 2 * YW - TY; }
-  const int halo_off = ((y0 + hly) & my) * nx + ((x0 + hlx) & mx);
+  const int halo_off = wrapm(y0 + hly, ny) * nx + wrapm(x0 + hlx, nx);
   // p points of this thread
   int p_off[NPP];
   bool p_ok[NPP];
@@ -728,10 +801,10 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
     const int idx = tid + 256 * t;
     p_ok[t] = idx < PW * PH;
     const int ly = idx / PW, lx = idx - ly * PW;
-    p_off[t] = ((y0 + ly) & my) * nx + ((x0 + lx) & mx);
+    p_off[t] = wrapm(y0 + ly, ny) * nx + wrapm(x0 + lx, nx);
   }
 
-  auto pz_of = [&](int zz) { return (long long)(zz & mz) * plane; };
+  auto pz_of = [&](int zz) { return (long long)(zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz)) * plane; };
   auto fetch_plane = [&](int zz, RawX* own, RawX& halo, float* vv) {
     const long long pz = pz_of(zz);
 #pragma unroll
@@ -981,7 +1054,7 @@ __global__ void __launch_bounds__(256) k_fold(Dims d, const float* __restrict__ 
     const long long r = t / (P + 1);
     const int ky = (int)(r % d.ny);
     const int kz = (int)(r / d.ny);
-    const int nkx = (d.nx - kx) & (d.nx - 1), nky = (d.ny - ky) & (d.ny - 1), nkz = (d.nz - kz) & (d.nz - 1);
+    const int nkx = (d.nx - kx) % d.nx, nky = (d.ny - ky) % d.ny, nkz = (d.nz - kz) % d.nz;
     const long long ik = ((long long)kz * d.ny + ky) * d.nx + kx;
     const long long in = ((long long)nkz * d.ny + nky) * d.nx + nkx;
     const double wk = w[ik], wn = w[in];
@@ -1071,9 +1144,9 @@ __global__ void __launch_bounds__(256) k_reweight(Dims d, const float* __restric
     const int x = (int)(i % d.nx);
     const int y = (int)((i / d.nx) % d.ny);
     const int z = (int)(i / plane);
-    const long long ixm = i - x + ((x - 1) & (d.nx - 1));
-    const long long iym = i + (long long)(((y - 1) & (d.ny - 1)) - y) * d.nx;
-    const long long izm = i + (long long)(((z - 1) & (d.nz - 1)) - z) * plane;
+    const long long ixm = i - x + (x == 0 ? d.nx - 1 : x - 1);
+    const long long iym = i + (long long)((y == 0 ? d.ny - 1 : y - 1) - y) * d.nx;
+    const long long izm = i + (long long)((z == 0 ? d.nz - 1 : z - 1) - z) * plane;
     const double xc = load_x<COMP>(hi, lo, i);
     const double ddx = xc - load_x<COMP>(hi, lo, ixm);
     const double ddy = xc - load_x<COMP>(hi, lo, iym);
@@ -1128,7 +1201,7 @@ __global__ void __launch_bounds__(256) k_fsc_shells(Dims d, const float2* __rest
     if (kx > 0) {
       acc(fsc_shell(kz, ky, kx, d), 2.0, f, g);
     } else {
-      const long long tp = ((long long)((d.nz - kz) & (d.nz - 1)) * d.ny + ((d.ny - ky) & (d.ny - 1))) * P;
+      const long long tp = ((long long)((d.nz - kz) % d.nz) * d.ny + ((d.ny - ky) % d.ny)) * P;
       const float2 fp = S1[tp], gp = S2[tp];
       const float2 f0 = make_float2(0.5f * (f.x + fp.x), 0.5f * (f.y - fp.y));
       const float2 fn = make_float2(0.5f * (f.y + fp.y), -0.5f * (f.x - fp.x));
@@ -1215,7 +1288,8 @@ __global__ void __launch_bounds__(256) k_adj_tv(Dims dm, const float* __restrict
   __shared__ double s_red[8];
   const int nx = dm.nx, ny = dm.ny, nz = dm.nz;
   const long long plane = (long long)nx * ny;
-  auto idx = [&](int z, int y, int x) { return (long long)(z & (nz - 1)) * plane + (long long)(y & (ny - 1)) * nx + (x & (nx - 1)); };
+  auto wr = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
+  auto idx = [&](int z, int y, int x) { return (long long)wr(z, nz) * plane + (long long)wr(y, ny) * nx + wr(x, nx); };
   auto Y = [&](long long i) { return xk[i] + m * (xk[i] - xkm[i]); };
   auto point = [&](int z, int y, int x, float p[3], float q[3]) {
     const long long i = idx(z, y, x);
@@ -1257,7 +1331,7 @@ __global__ void __launch_bounds__(256) k_expand_bbar(Dims d, const float2* __res
     const int kx = (int)(i % d.nx);
     const int ky = (int)((i / d.nx) % d.ny);
     const int kz = (int)(i / ((long long)d.nx * d.ny));
-    const int nky = (d.ny - ky) & (d.ny - 1), nkz = (d.nz - kz) & (d.nz - 1);
+    const int nky = (d.ny - ky) % d.ny, nkz = (d.nz - kz) % d.nz;
     float2 val;
     if (kx == 0 || kx == P) {
       const float2 z1 = S[((long long)kz * d.ny + ky) * P];
@@ -1312,6 +1386,10 @@ __global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ parti
     case 128: { constexpr int L_ = 128; CALL; break; } \
     case 256: { constexpr int L_ = 256; CALL; break; } \
     case 512: { constexpr int L_ = 512; CALL; break; } \
+    case 80: { constexpr int L_ = 80; CALL; break; }   \
+    case 96: { constexpr int L_ = 96; CALL; break; }   \
+    case 160: { constexpr int L_ = 160; CALL; break; } \
+    case 192: { constexpr int L_ = 192; CALL; break; } \
     default: return hipErrorInvalidValue;              \
   }
 
@@ -1327,6 +1405,10 @@ static int tpt(int L) {
     case 128: t = FftPlan<128>::T; break;
     case 256: t = FftPlan<256>::T; break;
     case 512: t = FftPlan<512>::T; break;
+    case 80: t = FftPlan<80>::T; break;
+    case 96: t = FftPlan<96>::T; break;
+    case 160: t = FftPlan<160>::T; break;
+    case 192: t = FftPlan<192>::T; break;
     default: t = 0;
   }
   return t;

@@ -30,7 +30,8 @@ def _rand_inputs(shape, seed, uv=True):
 
 # ------------------------------------------------------------------ closed form (mu = 0)
 
-@pytest.mark.parametrize("shape", [(4, 4, 4), (8, 16, 32), (32, 16, 8), (64, 64, 64), (16, 128, 32), (4, 512, 8)])
+@pytest.mark.parametrize("shape", [(4, 4, 4), (8, 16, 32), (32, 16, 8), (64, 64, 64), (16, 128, 32), (4, 512, 8),
+                                   (160, 32, 192), (192, 160, 16)])
 @pytest.mark.parametrize("compensated", [True, False])
 def test_mu0_uniform_w_is_soft_thresholded_inverse_fft(shape, compensated):
     announce(f"mu0 closed form shape={shape} comp={compensated}")
@@ -77,7 +78,8 @@ def test_config1_plain_fp32_storage_parity():
     assert err < TOL
 
 
-@pytest.mark.parametrize("shape", [(8, 4, 16), (4, 32, 8), (16, 64, 32), (32, 8, 128), (128, 8, 64)])
+@pytest.mark.parametrize("shape", [(8, 4, 16), (4, 32, 8), (16, 64, 32), (32, 8, 128), (128, 8, 64),
+                                   (32, 192, 160), (160, 16, 192)])
 def test_ragged_shapes_weighted_parity(shape):
     announce(f"weighted u,v parity shape={shape}")
     w, b, u, v, x0 = _rand_inputs(shape, 3)
