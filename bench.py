@@ -126,6 +126,87 @@ def copy_calibration(gib: float = 1.0, reps: int = 5):
     print(json.dumps({"copy_bytes_each_way": n * 4, "reps": reps, "GBps_read_plus_write": 2 * n * 4 / dt / 1e9}))
 
 
+BATCH_SIZES = [128, 160, 192, 256, 256, 192, 160, 128]
+
+
+def batch_members(seed=0):
+    """The batching workload: two half-maps and six class volumes of uneven boxes, each with
+    its own blob truth (0.003 blobs per voxel on chains of 250), SNR ~ U[0.3, 1] and lambda,
+    mu = (0.01, 0.05) x U[0.5, 2] each."""
+    import numpy as np
+
+    from paper_1905_13408_amd import synth
+
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 4, 999]))
+    out = []
+    for i, n in enumerate(BATCH_SIZES):
+        nb = int(0.003 * n ** 3)
+        snr = float(rng.uniform(0.3, 1.0))
+        lam = 0.01 * float(rng.uniform(0.5, 2.0))
+        mu = 0.05 * float(rng.uniform(0.5, 2.0))
+        vol = synth.make_volume((n, n, n), nb, max(1, nb // 250), 1.2, 0.39 * n, snr, seed=seed, config_id=4,
+                                volume_id=i)
+        out.append(((n, n, n), vol, lam, mu))
+    return out
+
+
+def bench_batch(args):
+    """8 volumes x `iters` SPG iterations: one HIP graph per step versus eager launches."""
+    import torch
+
+    from paper_1905_13408_amd import spg
+
+    iters = args.iters or 200
+    t_gen = time.perf_counter()
+    members = batch_members()
+    print(f"# batch inputs generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    solvers = []
+    shapes_tuned = []
+    for shape, vol, lam, mu in members:
+        sv = spg.SPGSolver(shape, lam, mu, 1e-3, storage=args.storage)
+        sv.set_data(torch.from_numpy(vol.w).cuda(), torch.from_numpy(vol.b).cuda())
+        shapes_tuned.append(sv.autotune(3) if not args.no_autotune else sv.launch_shape())
+        solvers.append(sv)
+    batch = spg.SPGBatch(solvers)
+    vox_it = sum(int(sh[0]) ** 3 for sh, _, _, _ in members) * iters
+
+    def graph_step():
+        for sv in solvers:
+            sv.set_map(None)
+        batch.run(iters)
+
+    def eager_step():
+        for sv in solvers:
+            sv.set_map(None)
+            sv.run(iters)
+
+    res = {}
+    for name, fn in [("graph", graph_step), ("eager", eager_step)]:
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) / args.steps
+    line = {
+        "metric": "SPG volume-iterations/s, 8-volume batch {128,160,192,256,256,192,160,128}^3 in one HIP graph",
+        "value": len(solvers) * iters / res["graph"],
+        "unit": "volume-iterations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * res["graph"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch-8: boxes {BATCH_SIZES}, 0.003 blobs/voxel, SNR U[0.3,1], lambda/mu x U[0.5,2], "
+                               f"{iters} SPG iterations each", "storage": args.storage},
+        "voxel_iterations_per_s": vox_it / res["graph"],
+        "eager_ms_per_step": 1e3 * res["eager"],
+        "graph_speedup_vs_eager": res["eager"] / res["graph"],
+        "launch_shapes": shapes_tuned,
+    }
+    print(json.dumps(line))
+    batch.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +219,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel HIP events")
     ap.add_argument("--copy-calib", action="store_true", help="only run the copy kernel used to scale HBM counters")
+    ap.add_argument("--no-autotune", action="store_true", help="batch workload: keep the default launch shapes")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -154,6 +236,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calib:
         copy_calibration()
+        return
+    if args.config == 4:
+        bench_batch(args)
         return
 
     from paper_1905_13408_amd import profiling, spg, synth

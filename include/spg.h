@@ -159,6 +159,28 @@ spg_status spg_state_size(const spg_problem* P, size_t* bytes);
 spg_status spg_get_state(spg_problem* P, void* d_buf, size_t bytes);
 spg_status spg_set_state(spg_problem* P, const void* d_buf, size_t bytes);
 
+/* Launch shapes: columns per tile of the y and z transform passes (8 or 16) and the z-slab
+ * depth of the stencil kernel (4..512 planes).  spg_autotune times each knob in turn
+ * (coordinate search over {16, 8}, {16, 8}, {32, 16, 64}) on `iters` iterations from the
+ * zero map with HIP events and keeps the fastest; it leaves the map at 0 with the
+ * momentum restarted.  Results are bitwise independent of the launch shape. */
+spg_status spg_set_launch_shape(spg_problem* P, int32_t nt_y, int32_t nt_z, int32_t zc);
+spg_status spg_get_launch_shape(const spg_problem* P, int32_t* nt_y, int32_t* nt_z, int32_t* zc);
+spg_status spg_autotune(spg_problem* P, int32_t iters);
+
+/* Batches: independent problems of any sizes (gold-standard half-maps, class volumes)
+ * advanced together in one HIP graph.  spg_batch_create takes n (1..64) distinct problems
+ * and the caller's stream (hipStream_t, NULL = default), which waits for every graph; it
+ * creates its own launch stream and one capture stream per problem (default priority).  spg_batch_run(K) synchronises each
+ * problem's own stream, captures K iterations of every problem as parallel branches of one
+ * graph (kernel nodes only), launches it, and makes each problem's stream wait for it: the
+ * results equal K calls of spg_run per problem, bitwise.  spg_batch_destroy releases the
+ * streams, events and graph, not the problems. */
+typedef struct spg_batch spg_batch;
+spg_status spg_batch_create(spg_problem* const* problems, int32_t n, void* hip_stream, spg_batch** out);
+spg_status spg_batch_run(spg_batch* B, int32_t K);
+spg_status spg_batch_destroy(spg_batch* B);
+
 /* Reverse mode of an unrolled solve, for tuning lambda, mu and the data b: the gradient of
  * a scalar loss of x_K with respect to (lambda, mu, b) through K SPG iterations (eq 20-21
  * with momentum, lr = 1/L(mu) differentiated as well), by the chain rule with a.e.

@@ -140,6 +140,9 @@ struct spg_problem {
   double t = 1.0;        // FISTA t_j
   double m_cur = 0.0;    // momentum m_j of y_j
   char err[512] = {0};
+  // launch shapes (chosen by spg_autotune): columns per tile of the y and z passes, z-slab
+  // depth of the stencil kernel
+  int nt_y = 16, nt_z = 16, zc = PT_ZC;
   // unrolled solve recorded by spg_run_checkpointed for spg_vjp
   bool vjp_valid = false;
   int32_t vjp_K = 0, vjp_C = 0;
@@ -241,10 +244,12 @@ spg_status gradient_pipeline(spg_problem* P, bool obj, int* nA, int* nB, void* g
   const float* wsp = P->at<float>(P->lay.ws);
   const float2* csp = P->at<float2>(P->lay.cs);
   prof_begin(P, SPG_KERNEL_FFT_Y_FWD);
-  SPG_CK(P, launch_fft_cols(d, P->S(), 1, 0, twy, nullptr, nullptr, nullptr, st, nullptr));
+  SPG_CK(P, launch_fft_cols(d, P->S(), 1, 0, twy, nullptr, nullptr, nullptr, st, nullptr, P->nt_y));
   prof_end(P, SPG_KERNEL_FFT_Y_FWD);
   prof_begin(P, SPG_KERNEL_FFT_Z_WEIGHT);
-  SPG_CK(P, launch_fft_cols(d, P->S(), 2, obj ? 3 : 2, twz, wsp, csp, obj ? P->part() + kPartA : nullptr, st, nA));
+  // the objective variant writes one partial per block: 16-column tiles keep <= 8192 blocks
+  SPG_CK(P, launch_fft_cols(d, P->S(), 2, obj ? 3 : 2, twz, wsp, csp, obj ? P->part() + kPartA : nullptr, st, nA,
+                            obj ? 16 : P->nt_z));
   prof_end(P, SPG_KERNEL_FFT_Z_WEIGHT);
   prof_begin(P, SPG_KERNEL_DC_NYQUIST);
   SPG_CK(P, launch_dc_nyquist(d, P->S(), twz, P->at<float>(P->lay.w0p), P->at<float>(P->lay.wnyq),
@@ -252,7 +257,7 @@ spg_status gradient_pipeline(spg_problem* P, bool obj, int* nA, int* nB, void* g
                               obj ? P->part() + kPartB : nullptr, st, nB));
   prof_end(P, SPG_KERNEL_DC_NYQUIST);
   prof_begin(P, SPG_KERNEL_FFT_Y_INV);
-  SPG_CK(P, launch_fft_cols(d, P->S(), 1, 1, twy, nullptr, nullptr, nullptr, st, nullptr));
+  SPG_CK(P, launch_fft_cols(d, P->S(), 1, 1, twy, nullptr, nullptr, nullptr, st, nullptr, P->nt_y));
   prof_end(P, SPG_KERNEL_FFT_Y_INV);
   prof_begin(P, SPG_KERNEL_C2R_X);
   SPG_CK(P, launch_c2r_x(d, P->S(), gout, gout_bf16, P->at<float2>(P->lay.tw_m), P->at<float2>(P->lay.tw_n), st));
@@ -293,6 +298,7 @@ ProxArgs prox_args(spg_problem* P, int nxt, double m, double m_next) {
   a.lam = P->prm.lambda;
   a.mu = P->prm.mu;
   a.eps = (float)P->prm.eps;
+  a.zc = P->zc;
   return a;
 }
 
@@ -590,7 +596,9 @@ spg_status spg_final_check(spg_problem* P, double* F_eps, double* F_0, double* k
   ProxArgs a = prox_args(P, P->cur, 0.0, 0.0);
   a.read_old = 0;
   a.gin = P->xhi(spare);
-  const int nC = prox_num_blocks(d);
+  // check-mode partials: 6 per block, at most 8192 blocks
+  while (prox_num_blocks(d, a.zc) > 8192) a.zc *= 2;
+  const int nC = prox_num_blocks(d, a.zc);
   a.partials = P->part() + kPartC;
   prof_begin(P, SPG_KERNEL_PROX_TV);
   SPG_CK(P, launch_prox_tv(d, a, P->store, true, P->stream));
@@ -705,6 +713,200 @@ spg_status spg_fsc(int32_t nx, int32_t ny, int32_t nz, const float* d_map1, cons
     const double den = std::sqrt(h[nshells + sidx] * h[2 * (size_t)nshells + sidx]);
     h_fsc[sidx] = den > 0 ? h[sidx] / den : 0.0;
   }
+  return SPG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- launch-shape autotuner
+
+extern "C" {
+
+spg_status spg_set_launch_shape(spg_problem* P, int32_t nt_y, int32_t nt_z, int32_t zc) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if ((nt_y != 8 && nt_y != 16) || (nt_z != 8 && nt_z != 16) || zc < 4 || zc > 512)
+    return set_err(P, SPG_E_INVAL, "nt_y, nt_z must be 8 or 16 and zc in [4, 512]");
+  P->nt_y = nt_y;
+  P->nt_z = nt_z;
+  P->zc = zc;
+  return SPG_OK;
+}
+
+spg_status spg_get_launch_shape(const spg_problem* P, int32_t* nt_y, int32_t* nt_z, int32_t* zc) {
+  if (!P) return SPG_E_INVAL;
+  if (nt_y) *nt_y = P->nt_y;
+  if (nt_z) *nt_z = P->nt_z;
+  if (zc) *zc = P->zc;
+  return SPG_OK;
+}
+
+spg_status spg_autotune(spg_problem* P, int32_t iters) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if (iters < 1 || iters > 1000) return set_err(P, SPG_E_INVAL, "iters must be in [1, 1000]");
+  if (!P->data_set) return set_err(P, SPG_E_STATE, "spg_set_data has not succeeded");
+  if (P->prof_on) return set_err(P, SPG_E_STATE, "profiling is active");
+  // coordinate search: for each knob, time its kernel class over `iters` iterations from
+  // the zero map for every candidate and keep the fastest
+  struct Knob {
+    int* val;
+    int cls;
+    std::vector<int> cand;
+  };
+  std::vector<Knob> knobs = {{&P->nt_y, SPG_KERNEL_FFT_Y_FWD, {16, 8}},
+                             {&P->nt_z, SPG_KERNEL_FFT_Z_WEIGHT, {16, 8}},
+                             {&P->zc, SPG_KERNEL_PROX_TV, {32, 16, 64}}};
+  for (Knob& kb : knobs) {
+    int best = *kb.val;
+    double best_ms = 1e300;
+    for (int c : kb.cand) {
+      *kb.val = c;
+      if ((s = spg_set_map(P, nullptr))) return s;
+      if ((s = spg_run(P, 1, nullptr))) return s;  // warm
+      if ((s = spg_profile_begin(P, kb.cls, iters))) return s;
+      if ((s = spg_run(P, iters, nullptr))) return s;
+      double ms[SPG_KERNEL_COUNT];
+      int32_t n[SPG_KERNEL_COUNT];
+      if ((s = spg_profile_end(P, ms, n))) return s;
+      if (n[kb.cls] > 0 && ms[kb.cls] < best_ms) {
+        best_ms = ms[kb.cls];
+        best = c;
+      }
+    }
+    *kb.val = best;
+  }
+  return spg_set_map(P, nullptr);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches in one HIP graph
+
+struct spg_batch {
+  std::vector<spg_problem*> probs;
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork = nullptr, done = nullptr;
+  hipStream_t origin = nullptr;  // capture and launch stream (the legacy default stream cannot capture)
+  hipStream_t user = nullptr;    // the caller's stream, which waits for every graph
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+};
+
+namespace {
+void batch_release_graph(spg_batch* B) {
+  if (B->exec) {
+    (void)hipStreamSynchronize(B->origin);
+    (void)hipGraphExecDestroy(B->exec);
+    B->exec = nullptr;
+  }
+  if (B->graph) {
+    (void)hipGraphDestroy(B->graph);
+    B->graph = nullptr;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+spg_status spg_batch_create(spg_problem* const* problems, int32_t n, void* hip_stream, spg_batch** out) {
+  if (!out || !problems || n < 1 || n > 64) return SPG_E_INVAL;
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (!problems[i]) return SPG_E_INVAL;
+    for (int j = 0; j < i; ++j)
+      if (problems[j] == problems[i]) return SPG_E_INVAL;
+  }
+  spg_batch* B = new (std::nothrow) spg_batch();
+  if (!B) return SPG_E_NOMEM;
+  B->probs.assign(problems, problems + n);
+  B->user = reinterpret_cast<hipStream_t>(hip_stream);
+  bool ok = hipStreamCreateWithFlags(&B->origin, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&B->fork, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&B->done, hipEventDisableTiming) == hipSuccess;
+  B->streams.assign(n, nullptr);
+  B->join.assign(n, nullptr);
+  for (int i = 0; ok && i < n; ++i)
+    ok = hipStreamCreateWithFlags(&B->streams[i], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&B->join[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    spg_batch_destroy(B);
+    return SPG_E_DEVICE;
+  }
+  *out = B;
+  return SPG_OK;
+}
+
+spg_status spg_batch_destroy(spg_batch* B) {
+  if (!B) return SPG_E_INVAL;
+  batch_release_graph(B);
+  for (hipStream_t s : B->streams)
+    if (s) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : B->join)
+    if (e) (void)hipEventDestroy(e);
+  if (B->fork) (void)hipEventDestroy(B->fork);
+  if (B->done) (void)hipEventDestroy(B->done);
+  if (B->origin) (void)hipStreamDestroy(B->origin);
+  delete B;
+  return SPG_OK;
+}
+
+spg_status spg_batch_run(spg_batch* B, int32_t K) {
+  if (!B || K < 0) return SPG_E_INVAL;
+  for (spg_problem* P : B->probs) {
+    spg_status s = usable(P);
+    if (s) return s;
+    if (!P->data_set || !(P->L > 0)) return set_err(P, SPG_E_STATE, "spg_set_data has not succeeded");
+    if (P->prof_on) return set_err(P, SPG_E_STATE, "profiling is active");
+  }
+  if (K == 0) return SPG_OK;
+  batch_release_graph(B);
+  const int n = (int)B->probs.size();
+  // inputs set on the problems' own streams and the caller's stream must be complete
+  // before the graph starts
+  for (spg_problem* P : B->probs)
+    if (hipStreamSynchronize(P->stream) != hipSuccess) return fail_device(P, hipErrorUnknown, "stream sync");
+  if (hipStreamSynchronize(B->user) != hipSuccess) return fail_device(B->probs[0], hipErrorUnknown, "stream sync");
+  std::vector<hipStream_t> saved(n);
+  auto fail = [&](hipError_t e, const char* what) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(B->origin, &g);
+    if (g) (void)hipGraphDestroy(g);
+    for (int i = 0; i < n; ++i)
+      if (saved[i]) B->probs[i]->stream = saved[i];
+    for (spg_problem* P : B->probs) P->sticky = true;  // host state advanced past the device
+    return fail_device(B->probs[0], e, what);
+  };
+  hipError_t e = hipStreamBeginCapture(B->origin, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return fail_device(B->probs[0], e, "hipStreamBeginCapture");
+  if ((e = hipEventRecord(B->fork, B->origin)) != hipSuccess) return fail(e, "hipEventRecord");
+  for (int i = 0; i < n; ++i) {
+    spg_problem* P = B->probs[i];
+    if ((e = hipStreamWaitEvent(B->streams[i], B->fork, 0)) != hipSuccess) return fail(e, "hipStreamWaitEvent");
+    saved[i] = P->stream;
+    P->stream = B->streams[i];
+    P->vjp_valid = false;
+    for (int it = 0; it < K; ++it)
+      if (iterate_once(P, nullptr) != SPG_OK) return fail(hipErrorUnknown, P->err);
+    if ((e = hipEventRecord(B->join[i], B->streams[i])) != hipSuccess) return fail(e, "hipEventRecord");
+    if ((e = hipStreamWaitEvent(B->origin, B->join[i], 0)) != hipSuccess) return fail(e, "hipStreamWaitEvent");
+  }
+  e = hipStreamEndCapture(B->origin, &B->graph);
+  for (int i = 0; i < n; ++i) B->probs[i]->stream = saved[i];
+  if (e != hipSuccess) {
+    for (spg_problem* P : B->probs) P->sticky = true;
+    return fail_device(B->probs[0], e, "hipStreamEndCapture");
+  }
+  if ((e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0)) != hipSuccess ||
+      (e = hipGraphLaunch(B->exec, B->origin)) != hipSuccess || (e = hipEventRecord(B->done, B->origin)) != hipSuccess) {
+    for (spg_problem* P : B->probs) P->sticky = true;
+    return fail_device(B->probs[0], e, "graph launch");
+  }
+  // later work on each problem's own stream and on the caller's stream starts after the graph
+  for (spg_problem* P : B->probs)
+    if ((e = hipStreamWaitEvent(P->stream, B->done, 0)) != hipSuccess) return fail_device(P, e, "hipStreamWaitEvent");
+  if ((e = hipStreamWaitEvent(B->user, B->done, 0)) != hipSuccess) return fail_device(B->probs[0], e, "hipStreamWaitEvent");
   return SPG_OK;
 }
 

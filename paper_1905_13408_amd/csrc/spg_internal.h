@@ -17,7 +17,8 @@ struct Dims {
   long long nvox;
 };
 
-// Tile of the fused stencil / prox kernel: 64 x-columns by 8 y-rows, marched along z.
+// Tile of the fused stencil / prox kernel: 64 x-columns by 8 y-rows, marched along z over
+// slabs of ProxArgs::zc planes (PT_ZC by default; the autotuner may choose another depth).
 constexpr int PT_TX = 64;
 constexpr int PT_TY = 8;
 constexpr int PT_ZC = 32;
@@ -50,13 +51,14 @@ struct ProxArgs {
   double m, m_next;             // momentum for y_k and for y_{k+1}
   double lr, lam, mu, gamma;
   float eps;
+  int zc;                       // z-slab depth of one block
 };
 
-int prox_num_blocks(const Dims& d);
+int prox_num_blocks(const Dims& d, int zc);
 
 hipError_t launch_fft_cols(const Dims& d, float2* S, int axis /*1 = y, 2 = z*/, int mode,
                            const float2* tw, const float* ws, const float2* cs, double* partials,
-                           hipStream_t st, int* nblocks_out);
+                           hipStream_t st, int* nblocks_out, int nt = 16 /* columns per tile: 8 or 16 */);
 hipError_t launch_dc_nyquist(const Dims& d, float2* S, const float2* tw_z, const float* w0p,
                              const float* wnyq, const float2* c0p, const float2* cnyq, double* partials,
                              hipStream_t st, int* nblocks_out);

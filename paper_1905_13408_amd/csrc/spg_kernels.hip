@@ -769,8 +769,8 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
   const int bz = blk / (ntx * nty);
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int x0 = bx * TX, y0 = by * TY;
-  const int z0 = bz * PT_ZC;
-  const int z1 = min(z0 + PT_ZC, nz);
+  const int z0 = bz * a.zc;
+  const int z1 = min(z0 + a.zc, nz);
   const long long plane = (long long)nx * ny;
   // periodic wrap of a coordinate (any grid size; the offsets below are computed once per block)
   auto wrapm = [](int v, int n) { return ((v % n) + n) % n; };
@@ -1415,9 +1415,10 @@ static int tpt(int L) {
 }
 
 hipError_t launch_fft_cols(const Dims& d, float2* S, int axis, int mode, const float2* tw, const float* ws,
-                           const float2* cs, double* partials, hipStream_t st, int* nblocks_out) {
+                           const float2* cs, double* partials, hipStream_t st, int* nblocks_out, int nt) {
   const int L = axis == 1 ? d.ny : d.nz;
-  const int NT = d.P < 16 ? d.P : 16;
+  if (nt != 8 && nt != 16) return hipErrorInvalidValue;
+  const int NT = d.P < nt ? d.P : nt;
   const int ntiles = (d.P + NT - 1) / NT;
   const int nbatch = axis == 1 ? d.nz : d.ny;
   const long long pstride = axis == 1 ? (long long)d.P : (long long)d.ny * d.P;
@@ -1486,17 +1487,18 @@ hipError_t launch_c2r_x(const Dims& d, const float2* S, void* rout, bool rout_bf
   return hipGetLastError();
 }
 
-int prox_num_blocks(const Dims& d) {
+int prox_num_blocks(const Dims& d, int zc) {
   const int ntx = (d.nx + PT_TX - 1) / PT_TX;
   const int nty = (d.ny + PT_TY - 1) / PT_TY;
-  const int ntz = (d.nz + PT_ZC - 1) / PT_ZC;
+  const int ntz = (d.nz + zc - 1) / zc;
   return ntx * nty * ntz;
 }
 
 hipError_t launch_prox_tv(const Dims& d, const ProxArgs& a, int store, bool check, hipStream_t st) {
   const int ntx = (d.nx + PT_TX - 1) / PT_TX;
   const int nty = (d.ny + PT_TY - 1) / PT_TY;
-  const dim3 grid(prox_num_blocks(d)), block(256);
+  if (a.zc < 1) return hipErrorInvalidValue;
+  const dim3 grid(prox_num_blocks(d, a.zc)), block(256);
 #define SPG_PROX(ST_) \
   do { if (check) k_prox_tv<ST_, true><<<grid, block, 0, st>>>(a, ntx, nty); \
        else k_prox_tv<ST_, false><<<grid, block, 0, st>>>(a, ntx, nty); } while (0)

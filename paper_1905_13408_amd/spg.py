@@ -72,6 +72,12 @@ def lib() -> ctypes.CDLL:
         "spg_set_state": [P, P, c_size_t],
         "spg_profile_begin": [P, c_int32, c_int32],
         "spg_profile_end": [P, POINTER(c_double), POINTER(c_int32)],
+        "spg_set_launch_shape": [P, c_int32, c_int32, c_int32],
+        "spg_get_launch_shape": [P, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)],
+        "spg_autotune": [P, c_int32],
+        "spg_batch_create": [POINTER(P), c_int32, P, POINTER(P)],
+        "spg_batch_run": [P, c_int32],
+        "spg_batch_destroy": [P],
         "spg_vjp_workspace_size": [P, c_int32, c_int32, POINTER(c_size_t)],
         "spg_run_checkpointed": [P, c_int32, c_int32, P, c_size_t],
         "spg_vjp": [P, P, c_size_t, P, P, P, POINTER(c_double), POINTER(c_double)],
@@ -251,6 +257,19 @@ class SPGSolver:
         self._check(self._L.spg_profile_end(self._h, ms, n))
         return {k: (ms[i], n[i]) for i, k in enumerate(KERNELS)}
 
+    # ------------------------------------------------------------------ launch shapes
+    def autotune(self, iters: int = 3):
+        self._check(self._L.spg_autotune(self._h, int(iters)))
+        return self.launch_shape()
+
+    def launch_shape(self):
+        a, b, c = c_int32(), c_int32(), c_int32()
+        self._check(self._L.spg_get_launch_shape(self._h, byref(a), byref(b), byref(c)))
+        return a.value, b.value, c.value
+
+    def set_launch_shape(self, nt_y, nt_z, zc):
+        self._check(self._L.spg_set_launch_shape(self._h, int(nt_y), int(nt_z), int(zc)))
+
     # ------------------------------------------------------------------ reverse mode
     def run_checkpointed(self, K: int, C: int):
         """Restart at the current map and run K iterations, checkpointing every C."""
@@ -329,3 +348,38 @@ def fsc(map1, map2, nshells=None, stream=None):
     if st != SPG_OK:
         raise SPGError(st, L.spg_status_string(st).decode())
     return np.array(out[:], dtype=np.float64)
+
+
+class SPGBatch:
+    """Several independent SPGSolver problems advanced together in one HIP graph per run."""
+
+    def __init__(self, solvers, stream=None):
+        import torch
+
+        self.solvers = list(solvers)
+        self._L = lib()
+        dev = self.solvers[0].device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        arr = (c_void_p * len(self.solvers))(*[s.handle.value for s in self.solvers])
+        h = c_void_p()
+        st = self._L.spg_batch_create(arr, len(self.solvers), c_void_p(self.stream.cuda_stream), byref(h))
+        if st != SPG_OK:
+            raise SPGError(st, self._L.spg_status_string(st).decode())
+        self._h = h
+
+    def run(self, K: int):
+        st = self._L.spg_batch_run(self._h, int(K))
+        if st != SPG_OK:
+            msgs = [s._L.spg_last_error(s.handle).decode() for s in self.solvers]
+            raise SPGError(st, "; ".join(m for m in msgs if m))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.spg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

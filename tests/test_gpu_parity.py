@@ -447,3 +447,94 @@ def test_differentiation_workload_128_vs_fp64_reference():
     assert abs(lb - olb) <= 1e-3 * abs(olb)
     assert abs(mb - omb) <= 1e-3 * abs(omb)
     assert eb < 1e-3
+
+
+# ------------------------------------------------------------------ launch shapes, autotuner, batches
+
+def test_launch_shapes_are_bitwise_equivalent():
+    shape = (64, 64, 128)
+    announce("launch-shape invariance")
+    w, b, u, v, x0 = _rand_inputs(shape, 51)
+    outs = []
+    for ls in [(16, 16, 32), (8, 8, 16), (8, 16, 64), (16, 8, 4)]:
+        g = gpu_solver(shape, w, b, 0.02, 0.05, 1e-2, u=u, v=v, x0=x0)
+        g.set_launch_shape(*ls)
+        g.run(12)
+        outs.append((g.get_map(), g.final_check()))
+    for x, chk in outs[1:]:
+        assert torch.equal(x, outs[0][0])
+        assert abs(chk[0] - outs[0][1][0]) <= 1e-12 * abs(outs[0][1][0])
+
+
+def test_autotune_picks_candidates_and_resets():
+    shape = (64, 64, 64)
+    announce("autotune")
+    w, b, u, v, x0 = _rand_inputs(shape, 53)
+    g = gpu_solver(shape, w, b, 0.02, 0.05, 1e-2, x0=x0)
+    nt_y, nt_z, zc = g.autotune(2)
+    assert nt_y in (8, 16) and nt_z in (8, 16) and zc in (16, 32, 64)
+    assert float(g.get_map().abs().max()) == 0.0
+    g.run(10)
+    h = gpu_solver(shape, w, b, 0.02, 0.05, 1e-2)
+    h.run(10)
+    assert torch.equal(g.get_map(), h.get_map())
+
+
+def _batch_members(seed):
+    shapes = [(32, 32, 32), (64, 64, 64), (16, 32, 64), (32, 160, 32)]
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 1001]))
+    members = []
+    for i, shape in enumerate(shapes):
+        vol = synth.make_volume(shape, max(4, int(0.003 * np.prod(shape))), 2, 1.2, 0.35 * min(shape),
+                                float(rng.uniform(0.3, 1.0)), seed=seed, config_id=4, volume_id=i)
+        lam = 0.01 * float(rng.uniform(0.5, 2.0))
+        mu = 0.05 * float(rng.uniform(0.5, 2.0))
+        members.append((shape, vol, lam, mu))
+    return members
+
+
+def test_batch_graph_matches_eager_runs_bitwise():
+    announce("batch graph vs eager (two graph launches)")
+    members = _batch_members(61)
+    solvers, refs = [], []
+    for shape, vol, lam, mu in members:
+        for lst in (solvers, refs):
+            s = spg.SPGSolver(shape, lam, mu, 1e-3)
+            s.set_data(vol.w, vol.b)
+            s.set_map(None)
+            lst.append(s)
+    batch = spg.SPGBatch(solvers)
+    batch.run(7)
+    for r in refs:
+        r.run(7)
+    for s, r in zip(solvers, refs):
+        assert torch.equal(s.get_map(), r.get_map())
+    torch.cuda.synchronize()
+    solvers[1].reweight(0.01, 0.01)   # eager work between graph launches
+    refs[1].reweight(0.01, 0.01)
+    batch.run(9)
+    for r in refs:
+        r.run(9)
+    for s, r in zip(solvers, refs):
+        assert torch.equal(s.get_map(), r.get_map())
+    batch.close()
+
+
+def test_batch_member_160_vs_oracle():
+    shape = (160, 160, 160)
+    announce("batch member 160^3 vs oracle")
+    vol = synth.make_volume(shape, int(0.003 * 160 ** 3), 48, 1.2, 0.39 * 160, 0.6, seed=7, config_id=4, volume_id=1)
+    s = spg.SPGSolver(shape, 0.012, 0.06, 1e-3)
+    s.set_data(vol.w, vol.b)
+    s.set_map(None)
+    t = spg.SPGSolver((32, 32, 32), 0.01, 0.05, 1e-3)
+    v2 = synth.make_volume((32, 32, 32), 60, 1, 1.0, 12.0, 1.0, seed=0, config_id=4, volume_id=2)
+    t.set_data(v2.w, v2.b)
+    t.set_map(None)
+    batch = spg.SPGBatch([s, t])
+    batch.run(20)
+    p = oracle_problem(vol.w, vol.b, 0.012, 0.06, 1e-3)
+    err = rel_l2(to_np(s.get_map()), O.spg_solve(p, 20))
+    print(f"160^3 batch member rel L2 = {err:.3e}", flush=True)
+    assert err < TOL
+    batch.close()
