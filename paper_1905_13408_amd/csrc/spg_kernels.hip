@@ -757,12 +757,14 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
   constexpr int PW = TX + 1, PH = TY + 1;  // p plane with the +1 shell
   constexpr int NPP = (PW * PH + 255) / 256;
   constexpr int NHALO = 2 * YW + 2 * TY;
+  constexpr int NOWN = TY / 4;  // voxels per thread and plane: rows ty + 4 h
+  static_assert(TY % 4 == 0 && NHALO <= 256, "tile shape");
   __shared__ float sY[2][YH][YW];
   __shared__ float sP[2][3][PH][PW];
   __shared__ double s_red[8];
 
   const int tid = threadIdx.x;
-  const int tx = tid & 63, ty = tid >> 6;  // owns (tx, ty) and (tx, ty + 4)
+  const int tx = tid & 63, ty = tid >> 6;  // owns (tx, ty + 4 h), h < NOWN
   const int blk = blockIdx.x;
   const int bx = blk % ntx;
   const int by = (blk / ntx) % nty;
@@ -778,10 +780,10 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
   // own voxels: in-plane offsets
   const int gx = wrapm(x0 + tx, nx);
   const bool vx = (x0 + tx) < nx;
-  int own_off[2];
-  bool vown[2];
+  int own_off[NOWN];
+  bool vown[NOWN];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < NOWN; ++h) {
     own_off[h] = wrapm(y0 + ty + 4 * h, ny) * nx + gx;
     vown[h] = vx && (y0 + ty + 4 * h) < ny;
   }
@@ -808,7 +810,7 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
   auto fetch_plane = [&](int zz, RawX* own, RawX& halo, float* vv) {
     const long long pz = pz_of(zz);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) fetch_raw<COMP>(a, pz + own_off[h], own[h]);
+    for (int h = 0; h < NOWN; ++h) fetch_raw<COMP>(a, pz + own_off[h], own[h]);
     if (has_halo) fetch_raw<COMP>(a, pz + halo_off, halo);
 #pragma unroll
     for (int t = 0; t < NPP; ++t) vv[t] = (a.v && p_ok[t]) ? ld_real<BF>(a.v, pz + p_off[t]) : 1.0f;
@@ -817,7 +819,7 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
   auto fetch_out = [&](int zz, float* g, float* uu, float* xp) {
     const long long pz = (long long)zz * plane;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NOWN; ++h) {
       const long long i = pz + own_off[h];
       if constexpr (CHECK) g[h] = vown[h] ? a.gin[i] : 0.f;
       else g[h] = vown[h] ? ld_real<BF>(a.rbuf, i) : 0.f;
@@ -827,7 +829,7 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
   };
   auto store_plane = [&](int buf, const RawX* own, const RawX& halo, double* ys, double* xks) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NOWN; ++h) {
       double yv, xv;
       eval_raw<COMP>(a, own[h], yv, xv);
       ys[h] = yv;
@@ -873,12 +875,12 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
   };
 
   // ---- prologue: planes z0-1 and z0 into LDS, p(z0), and the first prefetches
-  RawX rown[2], rhalo;
+  RawX rown[NOWN], rhalo;
   float rv[NPP];
-  double own_y[2], own_xk[2], nxt_y[2], nxt_xk[2];
-  float g_cur[2], u_cur[2], xp_cur[2];
+  double own_y[NOWN], own_xk[NOWN], nxt_y[NOWN], nxt_xk[NOWN];
+  float g_cur[NOWN], u_cur[NOWN], xp_cur[NOWN];
   {
-    double dy_[2], dx_[2];
+    double dy_[NOWN], dx_[NOWN];
     fetch_plane(z0 - 1, rown, rhalo, rv);
     store_plane(0, rown, rhalo, dy_, dx_);
     fetch_plane(z0, rown, rhalo, rv);
@@ -896,8 +898,13 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
     float vv_use[NPP];
 #pragma unroll
     for (int t = 0; t < NPP; ++t) vv_use[t] = rv[t];
-    float g_use[2] = {g_cur[0], g_cur[1]}, u_use[2] = {u_cur[0], u_cur[1]};
-    float xp_use[2] = {xp_cur[0], xp_cur[1]};
+    float g_use[NOWN], u_use[NOWN], xp_use[NOWN];
+#pragma unroll
+    for (int h = 0; h < NOWN; ++h) {
+      g_use[h] = g_cur[h];
+      u_use[h] = u_cur[h];
+      xp_use[h] = xp_cur[h];
+    }
     // prefetch plane z+2 and the outputs' inputs of plane z+1
     if (z + 1 < z1) {
       fetch_plane(z + 2, rown, rhalo, rv);
@@ -908,7 +915,7 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
     __syncthreads();
     const long long pz = (long long)z * plane;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < NOWN; ++h) {
       const int ly = ty + 4 * h, lx = tx;
       const float gtv = sP[cur][0][ly][lx] + sP[cur][1][ly][lx] + sP[cur][2][ly][lx] - sP[cur][2][ly][lx + 1] -
                         sP[cur][1][ly + 1][lx] - sP[cur ^ 1][0][ly][lx];
@@ -960,10 +967,11 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
     }
     cur ^= 1;
     ycur ^= 1;
-    own_y[0] = nxt_y[0];
-    own_y[1] = nxt_y[1];
-    own_xk[0] = nxt_xk[0];
-    own_xk[1] = nxt_xk[1];
+#pragma unroll
+    for (int h = 0; h < NOWN; ++h) {
+      own_y[h] = nxt_y[h];
+      own_xk[h] = nxt_xk[h];
+    }
   }
   if constexpr (CHECK) {
     const int nb = gridDim.x;
