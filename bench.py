@@ -219,7 +219,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel HIP events")
     ap.add_argument("--copy-calib", action="store_true", help="only run the copy kernel used to scale HBM counters")
-    ap.add_argument("--no-autotune", action="store_true", help="batch workload: keep the default launch shapes")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -256,6 +256,9 @@ def main():
     out = torch.empty(shape, dtype=torch.float32, device="cuda")
     solver = spg.SPGSolver(shape, c["lam"], c["mu"], c["eps"], storage=storage)
     rounds, iters = c["rounds"], c["iters"]
+    solver.set_data(w, b)
+    launch_shape = solver.launch_shape() if args.no_autotune else solver.autotune(3)
+    print(f"# launch shape (nt_y, nt_z, zc) = {launch_shape}", file=sys.stderr, flush=True)
 
     result = {}
 
@@ -310,7 +313,8 @@ def main():
                    "iterate_storage": {"compensated": "fp32 hi + bf16 lo iterate, fp64 prox",
                                        "fp32": "fp32 iterate",
                                        "bf16": "fp32 iterate, bf16 weights and map buffer"}[storage],
-                   "step": "set data + solve + fetch map + fp64 objective/KKT check"},
+                   "step": "set data + solve + fetch map + fp64 objective/KKT check",
+                   "launch_shape_nt_y_nt_z_zc": list(launch_shape)},
         "ms_per_iteration": 1e3 * elapsed / total_iters,
         "model_bytes_per_iteration": it_bytes,
         "model_GBps": it_bytes * value / 1e9,

@@ -202,6 +202,22 @@ spg_status spg_run_checkpointed(spg_problem* P, int32_t K, int32_t C, void* d_vj
 spg_status spg_vjp(spg_problem* P, void* d_vjp_ws, size_t bytes, const float* d_w, const float* d_xbar,
                    float* d_bbar, double* lam_bar, double* mu_bar);
 
+/* Backprojection as local kernel regression (section 2.2, eq 24-29), the producer of the
+ * solver's inputs: image i's Fourier coefficient X at signed frequency (u, v) (2D FFT order,
+ * v slow, u fast) lands at c = R_i (u, v, 0)^T (eq 24, c in (x, y, z) order) and is spread
+ * over the 27 grid points round(c) + {-1, 0, 1}^3 (round(t) = floor(t + 1/2), periodic
+ * wrap) with K = exp(-|c - n|^2 / h) (the paper uses h = 2), accumulating
+ * num += p_i K CTF X and N += p_i K CTF^2 (eq 28).  Writes w = N (nz*ny*nx float) and
+ * b = num / N (0 where N = 0; nz*ny*nx complex, interleaved), ready for spg_set_data.
+ * d_images: n_img*m*m complex; d_rot: n_img row-major 3x3 double matrices; d_ctf: n_img*m*m
+ * float or NULL (1); d_weight: n_img posterior weights or NULL (1).  Device pointers; the
+ * workspace (spg_backproject_workspace_size bytes, 8-byte aligned) holds fp64 accumulators;
+ * asynchronous on hip_stream.  fp64 atomics: sums can differ between runs in the last bits. */
+spg_status spg_backproject_workspace_size(int32_t nx, int32_t ny, int32_t nz, size_t* bytes);
+spg_status spg_backproject(int32_t nx, int32_t ny, int32_t nz, int32_t n_img, int32_t m, const float* d_images,
+                           const double* d_rot, const float* d_ctf, const float* d_weight, double h,
+                           void* d_workspace, size_t bytes, void* hip_stream, float* d_w_out, float* d_b_out);
+
 /* Gold-standard Fourier shell correlation of eq 30 (section 2.3) between two real maps
  * d_map1, d_map2 (nz*ny*nx float each, each axis as in spg_params):
  *   FSC(s) = Re sum_{k in s} F conj G / sqrt(sum_{k in s} |F|^2 sum_{k in s} |G|^2)

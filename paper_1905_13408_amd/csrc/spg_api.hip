@@ -1122,6 +1122,35 @@ spg_status spg_vjp(spg_problem* P, void* d_vjp_ws, size_t bytes, const float* d_
 
 }  // extern "C"
 
+// ---------------------------------------------------------------- backprojection
+
+extern "C" {
+
+spg_status spg_backproject_workspace_size(int32_t nx, int32_t ny, int32_t nz, size_t* bytes) {
+  if (!bytes || nx < 1 || ny < 1 || nz < 1 || nx > 1024 || ny > 1024 || nz > 1024) return SPG_E_INVAL;
+  *bytes = align_up(3 * (size_t)nx * ny * nz * sizeof(double));
+  return SPG_OK;
+}
+
+spg_status spg_backproject(int32_t nx, int32_t ny, int32_t nz, int32_t n_img, int32_t m, const float* d_images,
+                           const double* d_rot, const float* d_ctf, const float* d_weight, double h,
+                           void* d_workspace, size_t bytes, void* hip_stream, float* d_w_out, float* d_b_out) {
+  size_t need = 0;
+  if (spg_backproject_workspace_size(nx, ny, nz, &need) != SPG_OK) return SPG_E_INVAL;
+  if (n_img < 1 || m < 1 || m > 4096 || !std::isfinite(h) || h <= 0 || !d_images || !d_rot || !d_workspace ||
+      !d_w_out || !d_b_out || (reinterpret_cast<uintptr_t>(d_workspace) % 8) != 0)
+    return SPG_E_INVAL;
+  if (bytes < need) return SPG_E_NOMEM;
+  Dims d{nx, ny, nz, nx / 2, (long long)nx * ny * nz};
+  if (launch_backproject(d, n_img, m, reinterpret_cast<const float2*>(d_images), d_rot, d_ctf, d_weight, h,
+                         reinterpret_cast<double*>(d_workspace), d_w_out, reinterpret_cast<float2*>(d_b_out),
+                         reinterpret_cast<hipStream_t>(hip_stream)) != hipSuccess)
+    return SPG_E_DEVICE;
+  return SPG_OK;
+}
+
+}  // extern "C"
+
 // ---------------------------------------------------------------- checkpoints
 
 struct StateHeader {

@@ -1357,6 +1357,67 @@ __global__ void __launch_bounds__(256) k_expand_bbar(Dims d, const float2* __res
   }
 }
 
+// ---------------------------------------------------------------- backprojection (eq 24-29)
+// One thread per (image, pixel): the coefficient X at signed frequency (u, v) lands at
+// c = R (u, v, 0)^T (eq 24) and is spread over the 3^3 grid points round(c) + delta with
+// K = exp(-|c - n|^2 / h), accumulating num += p K ctf X and N += p K ctf^2 (eq 28) in fp64
+// atomics.  The coordinate products are rounded separately (no fused multiply-add) so that
+// the rounding of c, which decides the neighbourhood, is the reference's.
+__global__ void __launch_bounds__(256) k_backproject(Dims d, int n_img, int m, const float2* __restrict__ images,
+                                                     const double* __restrict__ rots, const float* __restrict__ ctf,
+                                                     const float* __restrict__ weights, double h,
+                                                     double* __restrict__ acc) {
+  const long long npix = (long long)m * m;
+  const long long total = npix * n_img;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total; t += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(t / npix);
+    const int pix = (int)(t - (long long)i * npix);
+    const int vi = pix / m, ui = pix - vi * m;
+    const double u = ui < (m + 1) / 2 ? ui : ui - m;
+    const double v = vi < (m + 1) / 2 ? vi : vi - m;
+    const double* R = rots + 9LL * i;
+    double c[3];
+    long long base[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      c[a] = __dadd_rn(__dmul_rn(R[3 * a + 0], u), __dmul_rn(R[3 * a + 1], v));
+      base[a] = (long long)floor(__dadd_rn(c[a], 0.5));
+    }
+    const float2 X = images[t];
+    const double cf = ctf ? (double)ctf[t] : 1.0;
+    const double p = weights ? (double)weights[i] : 1.0;
+    const double wr = p * cf * X.x, wi = p * cf * X.y, ww = p * cf * cf;
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const long long gx = base[0] + dx, gy = base[1] + dy, gz = base[2] + dz;
+          const double ex = c[0] - (double)gx, ey = c[1] - (double)gy, ez = c[2] - (double)gz;
+          const double K = exp(-(ex * ex + ey * ey + ez * ez) / h);
+          const long long ix = ((gx % d.nx) + d.nx) % d.nx, iy = ((gy % d.ny) + d.ny) % d.ny,
+                          iz = ((gz % d.nz) + d.nz) % d.nz;
+          const long long idx = (iz * d.ny + iy) * d.nx + ix;
+          atomicAdd(&acc[idx], K * wr);
+          atomicAdd(&acc[d.nvox + idx], K * wi);
+          atomicAdd(&acc[2 * d.nvox + idx], K * ww);
+        }
+  }
+}
+
+// w = N, b = num / N (0 where N = 0).
+__global__ void k_backproject_final(long long n, const double* __restrict__ acc, float* __restrict__ w,
+                                    float2* __restrict__ b) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const double den = acc[2 * n + i];
+    w[i] = (float)den;
+    b[i] = den > 0 ? make_float2((float)(acc[i] / den), (float)(acc[n + i] / den)) : make_float2(0.f, 0.f);
+  }
+}
+
+__global__ void k_fill_f64(double* __restrict__ dst, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = 0.0;
+}
+
 struct RedOps {
   int op[8];
 };
@@ -1620,6 +1681,21 @@ hipError_t launch_adj_tv(const Dims& d, const float* xk, const float* xkm, float
 
 hipError_t launch_expand_bbar(const Dims& d, const float2* S, const float* w, float2* out, hipStream_t st) {
   k_expand_bbar<<<ew_grid(d.nvox), 256, 0, st>>>(d, S, w, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_backproject(const Dims& d, int n_img, int m, const float2* images, const double* rots,
+                              const float* ctf, const float* weights, double h, double* acc, float* w, float2* b,
+                              hipStream_t st) {
+  k_fill_f64<<<ew_grid(3 * d.nvox), 256, 0, st>>>(acc, 3 * d.nvox);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long long total = (long long)n_img * m * m;
+  long long g = (total + 255) / 256;
+  if (g > 65536) g = 65536;
+  k_backproject<<<(unsigned)g, 256, 0, st>>>(d, n_img, m, images, rots, ctf, weights, h, acc);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_backproject_final<<<ew_grid(d.nvox), 256, 0, st>>>(d.nvox, acc, w, b);
   return hipGetLastError();
 }
 

@@ -81,6 +81,8 @@ def lib() -> ctypes.CDLL:
         "spg_vjp_workspace_size": [P, c_int32, c_int32, POINTER(c_size_t)],
         "spg_run_checkpointed": [P, c_int32, c_int32, P, c_size_t],
         "spg_vjp": [P, P, c_size_t, P, P, P, POINTER(c_double), POINTER(c_double)],
+        "spg_backproject_workspace_size": [c_int32, c_int32, c_int32, POINTER(c_size_t)],
+        "spg_backproject": [c_int32, c_int32, c_int32, c_int32, c_int32, P, P, P, P, c_double, P, c_size_t, P, P, P],
         "spg_fsc_workspace_size": [c_int32, c_int32, c_int32, c_int32, POINTER(c_size_t)],
         "spg_fsc": [c_int32, c_int32, c_int32, P, P, c_int32, P, c_size_t, P, POINTER(c_double)],
     }
@@ -383,3 +385,35 @@ class SPGBatch:
             self.close()
         except Exception:
             pass
+
+
+def backproject(shape, images, rots, ctf=None, weights=None, h=2.0, stream=None):
+    """Gaussian-kernel backprojection of eq 24-29 on the device: returns (w, b) tensors.
+
+    images: (n_img, m, m) complex64; rots: (n_img, 3, 3) float64; ctf: (n_img, m, m) float32
+    or None; weights: (n_img,) float32 or None; all on the same CUDA device.
+    """
+    import torch
+
+    nz, ny, nx = (int(s) for s in shape)
+    images = images.to(torch.complex64).contiguous()
+    n_img, m, _ = images.shape
+    dev = images.device
+    rots = rots.to(device=dev, dtype=torch.float64).contiguous()
+    ctf = None if ctf is None else ctf.to(device=dev, dtype=torch.float32).contiguous()
+    weights = None if weights is None else weights.to(device=dev, dtype=torch.float32).contiguous()
+    L = lib()
+    n = c_size_t(0)
+    st = L.spg_backproject_workspace_size(nx, ny, nz, byref(n))
+    if st != SPG_OK:
+        raise SPGError(st, L.spg_status_string(st).decode())
+    ws = torch.empty(n.value, dtype=torch.uint8, device=dev)
+    w = torch.empty(shape, dtype=torch.float32, device=dev)
+    b = torch.empty(shape, dtype=torch.complex64, device=dev)
+    stream = stream if stream is not None else torch.cuda.current_stream(dev)
+    st = L.spg_backproject(nx, ny, nz, n_img, m, _ptr(torch.view_as_real(images)), _ptr(rots), _ptr(ctf), _ptr(weights),
+                           float(h), _ptr(ws), n, c_void_p(stream.cuda_stream), _ptr(w), _ptr(torch.view_as_real(b)))
+    if st != SPG_OK:
+        raise SPGError(st, L.spg_status_string(st).decode())
+    torch.cuda.current_stream(dev).synchronize()
+    return w, b
