@@ -239,21 +239,28 @@ __device__ __forceinline__ void fft_stage(float* __restrict__ re, float* __restr
   __syncthreads();
 }
 
-template <int L, int S, bool INV>
+template <int L, int TT, int S, bool INV>
 __device__ __forceinline__ void lds_stages(float* re, float* im, int ps, int q, int Ns, const float2* tw) {
   constexpr RadixList pl = make_plan(L);
   if constexpr (S < pl.n) {
     constexpr int R = pl.r[S];
-    fft_stage<L, FftPlan<L>::T, R, INV>(re, im, ps, q, Ns, tw);
-    lds_stages<L, S + 1, INV>(re, im, ps, q, Ns * R, tw);
+    fft_stage<L, TT, R, INV>(re, im, ps, q, Ns, tw);
+    lds_stages<L, TT, S + 1, INV>(re, im, ps, q, Ns * R, tw);
   }
 }
 
-template <int L, bool INV>
+template <int L, bool INV, int TT = FftPlan<L>::T>
 __device__ __forceinline__ void fft_lds(float* re, float* im, int ps, int q, const float2* __restrict__ tw) {
   __syncthreads();
-  lds_stages<L, 0, INV>(re, im, ps, q, 1, tw);
+  lds_stages<L, TT, 0, INV>(re, im, ps, q, 1, tw);
 }
+
+// Threads per column of the packed kx = 0 / nx/2 plane kernel: only ny/2 + 1 blocks of two
+// columns run, so each column gets as many threads as its radix plan allows (up to 64).
+template <int L>
+struct DcT {
+  static constexpr int T = largest_divisor_le(plan_gcd(L), 64);
+};
 
 // Register-resident variant.  Thread q of a transform owns the points q + T i,
 // i in [0, E), E = L / T, held in a[i].  The first stage reads its butterfly inputs
@@ -350,12 +357,13 @@ __device__ __forceinline__ void fft_reg(float2 (&a)[reg_e(L, TT)], float* re, fl
   reg_stages<L, TT, 0, INV>(a, re, im, ps, q, twl);
 }
 
-// Threads per column of the column passes: more threads for the long axes keeps the
-// per-thread state of the fused z pass (data, folded weight and data term) small
-// enough for two 512-thread blocks per CU.
+// Threads per column of the column passes: more threads for the long axes keep the
+// per-thread state of the fused z pass (data, folded weight and data term) small.  At
+// 512 points, 64 threads of 8 values each hold it near 110 VGPRs, so a 16-column tile
+// is one 1024-thread block per CU and an 8-column tile runs two blocks per CU.
 template <int L>
 struct ColT {
-  static constexpr int T = (L >= 256 && (L & (L - 1)) == 0) ? 32 : FftPlan<L>::T;
+  static constexpr int T = L == 512 ? 64 : ((L >= 256 && (L & (L - 1)) == 0) ? 32 : FftPlan<L>::T);
 };
 
 // ---------------------------------------------------------------- XCD-aware block order
@@ -404,14 +412,14 @@ __device__ double block_reduce(double v, double* sh) {
 // (multiplicity 2 for 0 < kx < nx/2; the kx = 0 column is done by k_dc_nyquist).
 
 template <int L, int MODE>
-__global__ void __launch_bounds__(512) k_fft_cols(float2* __restrict__ S, int P, int ntiles, long long pstride,
+__global__ void __launch_bounds__(1024) k_fft_cols(float2* __restrict__ S, int P, int ntiles, long long pstride,
                                                   long long bstride, const float2* __restrict__ tw,
                                                   const float* __restrict__ ws, const float2* __restrict__ cs,
                                                   double* __restrict__ partials, int NT) {
   __shared__ float s_re[L * 16];
   __shared__ float s_im[L * 16];
   __shared__ float2 s_tw[L];
-  __shared__ double s_red[8];
+  __shared__ double s_red[16];  // one slot per wave (up to 1024 threads)
   constexpr int T = ColT<L>::T;
   constexpr int E = RegPlan<L, T>::E;
   const int tid = threadIdx.x;
@@ -501,7 +509,7 @@ __global__ void __launch_bounds__(256) k_dc_nyquist(float2* __restrict__ S, int 
   __shared__ float s_re[L * 2];
   __shared__ float s_im[L * 2];
   __shared__ double s_red[8];
-  constexpr int T = FftPlan<L>::T;
+  constexpr int T = DcT<L>::T;
   constexpr int NE = (L + T - 1) / T;
   const int tid = threadIdx.x;
   const int c = tid & 1, q = tid >> 1;
@@ -520,7 +528,7 @@ __global__ void __launch_bounds__(256) k_dc_nyquist(float2* __restrict__ S, int 
     re[p * 2] = v.x;
     im[p * 2] = v.y;
   }
-  fft_lds<L, false>(re, im, 2, q, tw);
+  fft_lds<L, false, T>(re, im, 2, q, tw);
   float2 nv[NE];
   double acc = 0.0;
 #pragma unroll
@@ -560,7 +568,7 @@ __global__ void __launch_bounds__(256) k_dc_nyquist(float2* __restrict__ S, int 
       im[kz * 2] = nv[i].y;
     }
   }
-  fft_lds<L, true>(re, im, 2, q, tw);
+  fft_lds<L, true, T>(re, im, 2, q, tw);
   if (c == 0 || ky != kyp)
     for (int p = q; p < L; p += T) S[base + p * pstride] = make_float2(re[p * 2], im[p * 2]);
 }
@@ -765,7 +773,11 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
 
   const int tid = threadIdx.x;
   const int tx = tid & 63, ty = tid >> 6;  // owns (tx, ty + 4 h), h < NOWN
-  const int blk = blockIdx.x;
+  // consecutive tiles (one x row of tiles at nx = 512) on one XCD, so that the x-halo
+  // columns a tile reads are the L2 lines its neighbour tiles fetch
+  const int blk = (gridDim.x >= 64 && (int)blockIdx.x < (int)(gridDim.x & ~63u))
+                      ? (int)((blockIdx.x & ~63u) | ((blockIdx.x & 7u) << 3) | ((blockIdx.x >> 3) & 7u))
+                      : (int)blockIdx.x;
   const int bx = blk % ntx;
   const int by = (blk / ntx) % nty;
   const int bz = blk / (ntx * nty);
@@ -1492,8 +1504,8 @@ hipError_t launch_fft_cols(const Dims& d, float2* S, int axis, int mode, const f
   const int nbatch = axis == 1 ? d.nz : d.ny;
   const long long pstride = axis == 1 ? (long long)d.P : (long long)d.ny * d.P;
   const long long bstride = axis == 1 ? (long long)d.ny * d.P : (long long)d.P;
-  const int T = L >= 256 ? 32 : tpt(L);
-  if (T == 0) return hipErrorInvalidValue;
+  int T = 0;
+  SPG_DISPATCH_L(L, (T = ColT<L_>::T));
   const dim3 grid(ntiles * nbatch), block(NT * T);
   if (nblocks_out) *nblocks_out = ntiles * nbatch;
 #define SPG_COLS(MODE_) k_fft_cols<L_, MODE_><<<grid, block, 0, st>>>(S, d.P, ntiles, pstride, bstride, tw, ws, cs, partials, NT)
@@ -1512,8 +1524,8 @@ hipError_t launch_fft_cols(const Dims& d, float2* S, int axis, int mode, const f
 hipError_t launch_dc_nyquist(const Dims& d, float2* S, const float2* tw_z, const float* w0p, const float* wnyq,
                              const float2* c0p, const float2* cnyq, double* partials, hipStream_t st, int* nblocks_out) {
   const int L = d.nz;
-  const int T = tpt(L);
-  if (T == 0) return hipErrorInvalidValue;
+  int T = 0;
+  SPG_DISPATCH_L(L, (T = DcT<L_>::T));
   const dim3 grid(d.ny / 2 + 1), block(2 * T);
   if (nblocks_out) *nblocks_out = d.ny / 2 + 1;
   if (partials) {
