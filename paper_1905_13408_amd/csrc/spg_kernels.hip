@@ -4,7 +4,7 @@
 // One SPG iteration crosses HBM in these sweeps (all in place on the packed half
 // spectrum S except where noted):
 //   k_fft_cols<mode 0> (y axis)   forward column FFTs along y
-//   k_fft_cols<mode 2> (z axis)   forward FFT along z, G = w~ Y - c, inverse FFT along z
+//   k_fft_zw<mode 2>   (z axis)   forward FFT along z, G = w~ Y - c, inverse FFT along z
 //   k_dc_nyquist                  the same for the packed kx = 0 / kx = nx/2 plane
 //   k_fft_cols<mode 1> (y axis)   inverse column FFTs along y
 //   k_c2r_x                       x-axis inverse real FFT -> data gradient map
@@ -406,20 +406,30 @@ __device__ double block_reduce(double v, double* sh) {
 
 // ---------------------------------------------------------------- column FFT passes
 // Tile: NT consecutive kx columns (<= 16, one 128-byte row segment) by the whole axis.
-// mode 0: forward; mode 1: inverse; mode 2: forward, G = ws*Y - cs, inverse (z axis);
-// mode 3: as 2 and also writes per-block partials of 1/2 ws |Y|^2 - Re(conj(cs) Y);
-// mode 4: forward, G = ws*Y, inverse (the data-term Hessian applied to a map)
-// (multiplicity 2 for 0 < kx < nx/2; the kx = 0 column is done by k_dc_nyquist).
+// k_fft_cols, one tile per block -- mode 0: forward; mode 1: inverse.
+// k_fft_zw, persistent blocks on the z axis -- mode 2: forward, G = ws*Y - cs, inverse;
+// mode 3: as 2 and also writes per-block partials of 1/2 ws |Y|^2 - Re(conj(cs) Y)
+// (multiplicity 2 for 0 < kx < nx/2; the kx = 0 column is done by k_dc_nyquist);
+// mode 4: forward, G = ws*Y, inverse (the data-term Hessian applied to a map).
+
+// Element access at a 32-bit byte offset from a block-uniform base pointer.
+template <typename V>
+__device__ __forceinline__ V ld_at(const V* __restrict__ base, unsigned boff) {
+  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + boff);
+}
+template <typename V>
+__device__ __forceinline__ void st_at(V* __restrict__ base, unsigned boff, V v) {
+  *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + boff) = v;
+}
 
 template <int L, int MODE>
-__global__ void __launch_bounds__(1024) k_fft_cols(float2* __restrict__ S, int P, int ntiles, long long pstride,
-                                                  long long bstride, const float2* __restrict__ tw,
-                                                  const float* __restrict__ ws, const float2* __restrict__ cs,
-                                                  double* __restrict__ partials, int NT) {
+__global__ void __launch_bounds__(16 * ColT<L>::T) k_fft_cols(float2* __restrict__ S, int P, int ntiles,
+                                                              long long pstride, long long bstride,
+                                                              const float2* __restrict__ tw, int NT) {
+  static_assert(MODE == 0 || MODE == 1, "single transforms");
   __shared__ float s_re[L * 16];
   __shared__ float s_im[L * 16];
   __shared__ float2 s_tw[L];
-  __shared__ double s_red[16];  // one slot per wave (up to 1024 threads)
   constexpr int T = ColT<L>::T;
   constexpr int E = RegPlan<L, T>::E;
   const int tid = threadIdx.x;
@@ -437,40 +447,101 @@ __global__ void __launch_bounds__(1024) k_fft_cols(float2* __restrict__ S, int P
   const int off0 = c + q * ps32;
   const int step = T * ps32;
 
-  // data loads first; the z pass issues the loads of the folded weight and data term
-  // after the first forward stage so that they are in flight during the later stages
   float2 a[E];
 #pragma unroll
   for (int i = 0; i < E; ++i) a[i] = valid ? Sb[off0 + i * step] : make_float2(0.f, 0.f);
   for (int i = tid; i < L; i += blockDim.x) s_tw[i] = tw[i];
   __syncthreads();
-  float* re = s_re + c;
-  float* im = s_im + c;
-  constexpr int NS = RegPlan<L, T>::ns;
-  float wv[MODE >= 2 ? E : 1];
-  float2 cv[MODE >= 2 ? E : 1];
-  if constexpr (MODE >= 2 && NS > 1) {
-    reg_stages<L, T, 0, false, 1>(a, re, im, NT, q, s_tw);
-    const float* __restrict__ wsb = ws + ub;
-    const float2* __restrict__ csb = cs + ub;
+  fft_reg<L, MODE == 1, T>(a, s_re + c, s_im + c, NT, q, s_tw);
+  if (valid) {
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-      wv[i] = valid ? wsb[off0 + i * step] : 0.f;
-      cv[i] = (valid && MODE != 4) ? csb[off0 + i * step] : make_float2(0.f, 0.f);
-    }
-    reg_stages<L, T, 1, false>(a, re, im, NT, q, s_tw);
-  } else {
-    if constexpr (MODE >= 2) {
-#pragma unroll
-      for (int i = 0; i < E; ++i) {
-        wv[i] = valid ? ws[ub + off0 + i * step] : 0.f;
-        cv[i] = (valid && MODE != 4) ? cs[ub + off0 + i * step] : make_float2(0.f, 0.f);
-      }
-    }
-    fft_reg<L, MODE == 1, T>(a, re, im, NT, q, s_tw);
+    for (int i = 0; i < E; ++i) Sb[off0 + i * step] = a[i];
   }
-  if constexpr (MODE >= 2) {
-    double acc = 0.0;
+}
+
+template <int L, int MODE>
+__global__ void __launch_bounds__(16 * ColT<L>::T) k_fft_zw(float2* __restrict__ S, int P, int ntiles, int total,
+                                                              long long pstride, long long bstride,
+                                                              const float2* __restrict__ tw,
+                                                              const float* __restrict__ ws,
+                                                              const float2* __restrict__ cs,
+                                                              double* __restrict__ partials, int NT) {
+  __shared__ float s_re[L * 16];
+  __shared__ float s_im[L * 16];
+  __shared__ float2 s_tw[L];
+  __shared__ double s_red[16];  // one slot per wave (up to 1024 threads)
+  constexpr int T = ColT<L>::T;
+  constexpr int E = RegPlan<L, T>::E;
+  const int tid = threadIdx.x;
+  const int c = tid % NT, q = tid / NT;
+  static_assert(MODE >= 2 && MODE <= 4, "fused z modes");
+  // Persistent blocks that load the next tile while transforming the current one: with a
+  // grid of 8k blocks, XCD x (= blockIdx % 8) owns the contiguous tile range
+  // [x chunk, (x+1) chunk) and its k-th block walks that range with stride k, so tiles
+  // that share 128-byte lines (the folded weight rows of neighbouring 16-column tiles)
+  // are in flight in one L2 at the same time.
+  const int G = gridDim.x;
+  const bool split = G >= 8 && (G & 7) == 0;
+  const int xcd = split ? (int)(blockIdx.x & 7u) : 0;
+  const int chunk = split ? (total + 7) >> 3 : total;
+  const int nb = split ? G >> 3 : G;
+  int t = xcd * chunk + (split ? (int)(blockIdx.x >> 3) : (int)blockIdx.x);
+  const int t_end = min(total, xcd * chunk + chunk);
+  // Block-uniform tile base pointers and unsigned 32-bit per-lane byte offsets of the
+  // complex elements (every offset in a column is below nz*ny*P*8 <= 2^29 bytes), so the
+  // loads take a scalar base and a 32-bit vector offset; the fp32 weight uses half the
+  // offset.  A lane whose column lies past the last kx reads column 0 of its tile instead
+  // (always in bounds) and stores nothing.
+  const unsigned ps = (unsigned)pstride;
+  const unsigned step = (unsigned)T * ps * 8u;
+  auto tile_base = [&](int tt) -> long long {
+    return (long long)(tt / ntiles) * bstride + (long long)(tt % ntiles) * NT;
+  };
+  auto lane_off = [&](int tt) -> unsigned {
+    return ((unsigned)((tt % ntiles) * NT + c < P ? c : 0) + (unsigned)q * ps) * 8u;
+  };
+
+  float2 a[E];
+  if (t < t_end) {
+    const float2* __restrict__ Sb = S + tile_base(t);
+    const unsigned o = lane_off(t);
+#pragma unroll
+    for (int i = 0; i < E; ++i) a[i] = ld_at(Sb, o + i * step);
+  }
+  for (int i = tid; i < L; i += blockDim.x) s_tw[i] = tw[i];
+  double acc = 0.0;
+  for (; t < t_end; t += nb) {
+    __syncthreads();  // twiddles visible; the previous tile's last stage read the LDS planes
+    // The lane indices pass through an empty asm statement so that the per-stage LDS
+    // addresses derived from them are formed inside the loop where they are used, not
+    // hoisted out of it and held in registers across all tiles.
+    int cl = c, ql = q;
+    asm volatile("" : "+v"(cl), "+v"(ql));
+    float* re = s_re + cl;
+    float* im = s_im + cl;
+    const long long ub = tile_base(t);
+    const int kx = (t % ntiles) * NT + cl;
+    const bool valid = kx < P;
+    const unsigned o = lane_off(t);
+    const int tn = t + nb;
+    const bool more = tn < t_end;  // block-uniform
+    float2 nxt[E];
+    float wv[E];
+    float2 cv[E];
+    reg_stages<L, T, 0, false, 1>(a, re, im, NT, ql, s_tw);
+    // the folded weight and data term load during the remaining forward stages
+    const float* __restrict__ wsb = ws + ub;
+#pragma unroll
+    for (int i = 0; i < E; ++i) wv[i] = ld_at(wsb, (o + i * step) >> 1);
+    if constexpr (MODE != 4) {
+      const float2* __restrict__ csb = cs + ub;
+#pragma unroll
+      for (int i = 0; i < E; ++i) cv[i] = ld_at(csb, o + i * step);
+    } else {
+#pragma unroll
+      for (int i = 0; i < E; ++i) cv[i] = make_float2(0.f, 0.f);
+    }
+    reg_stages<L, T, 1, false>(a, re, im, NT, ql, s_tw);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const float yr = a[i].x, yi = a[i].y;
@@ -481,16 +552,30 @@ __global__ void __launch_bounds__(1024) k_fft_cols(float2* __restrict__ S, int P
       }
       a[i] = make_float2(wv[i] * yr - cv[i].x, wv[i] * yi - cv[i].y);
     }
-    if constexpr (MODE == 3) {
-      double r = block_reduce<RED_OP_SUM>(acc, s_red);
-      if (tid == 0) partials[blk] = r;
-    }
     __syncthreads();  // the forward transform's last stage read the LDS planes
-    fft_reg<L, true, T>(a, re, im, NT, q, s_tw);
-  }
-  if (valid && !(MODE >= 2 && kx == 0)) {
+    reg_stages<L, T, 0, true, 1>(a, re, im, NT, ql, s_tw);
+    // the next tile loads during the remaining inverse stages
+    if (more) {
+      const float2* __restrict__ Sn = S + tile_base(tn);
+      const unsigned on = lane_off(tn);
 #pragma unroll
-    for (int i = 0; i < E; ++i) Sb[off0 + i * step] = a[i];
+      for (int i = 0; i < E; ++i) nxt[i] = ld_at(Sn, on + i * step);
+    }
+    reg_stages<L, T, 1, true>(a, re, im, NT, ql, s_tw);
+
+    if (valid && kx != 0) {  // the kx = 0 column belongs to k_dc_nyquist
+      float2* __restrict__ Sb = S + ub;
+#pragma unroll
+      for (int i = 0; i < E; ++i) st_at(Sb, o + i * step, a[i]);
+    }
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < E; ++i) a[i] = nxt[i];
+    }
+  }
+  if constexpr (MODE == 3) {
+    const double r = block_reduce<RED_OP_SUM>(acc, s_red);
+    if (tid == 0) partials[blockIdx.x] = r;
   }
 }
 
@@ -1495,10 +1580,38 @@ static int tpt(int L) {
   return t;
 }
 
+static int cu_count() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      n < 1)
+    return 256;
+  return n;
+}
+
+// Fused z passes: one persistent block per resident slot (CUs x blocks per CU), rounded
+// down to a multiple of the 8 XCDs, or one block per tile when there are fewer tiles.
+template <int L, int MODE>
+static hipError_t launch_zw(float2* S, int P, int ntiles, int total, long long pstride, long long bstride,
+                            const float2* tw, const float* ws, const float2* cs, double* partials, int NT, int T,
+                            hipStream_t st, int* nblocks_out) {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fft_zw<L, MODE>, NT * T, 0) != hipSuccess || occ < 1)
+    occ = 1;
+  long long g = (long long)cu_count() * occ;
+  if (g > 4096) g = 4096;  // the objective partials of mode 3 hold one value per block
+  if (g >= total) g = total;
+  else if (g >= 8) g &= ~7LL;
+  if (nblocks_out) *nblocks_out = (int)g;
+  k_fft_zw<L, MODE><<<dim3((unsigned)g), dim3(NT * T), 0, st>>>(S, P, ntiles, total, pstride, bstride, tw, ws, cs,
+                                                               partials, NT);
+  return hipGetLastError();
+}
+
 hipError_t launch_fft_cols(const Dims& d, float2* S, int axis, int mode, const float2* tw, const float* ws,
                            const float2* cs, double* partials, hipStream_t st, int* nblocks_out, int nt) {
   const int L = axis == 1 ? d.ny : d.nz;
   if (nt != 8 && nt != 16) return hipErrorInvalidValue;
+  if (mode < 0 || mode > 4 || (mode >= 2 && axis != 2)) return hipErrorInvalidValue;
   const int NT = d.P < nt ? d.P : nt;
   const int ntiles = (d.P + NT - 1) / NT;
   const int nbatch = axis == 1 ? d.nz : d.ny;
@@ -1506,19 +1619,26 @@ hipError_t launch_fft_cols(const Dims& d, float2* S, int axis, int mode, const f
   const long long bstride = axis == 1 ? (long long)d.ny * d.P : (long long)d.P;
   int T = 0;
   SPG_DISPATCH_L(L, (T = ColT<L_>::T));
-  const dim3 grid(ntiles * nbatch), block(NT * T);
-  if (nblocks_out) *nblocks_out = ntiles * nbatch;
-#define SPG_COLS(MODE_) k_fft_cols<L_, MODE_><<<grid, block, 0, st>>>(S, d.P, ntiles, pstride, bstride, tw, ws, cs, partials, NT)
-  switch (mode) {
-    case 0: SPG_DISPATCH_L(L, SPG_COLS(0)); break;
-    case 1: SPG_DISPATCH_L(L, SPG_COLS(1)); break;
-    case 2: SPG_DISPATCH_L(L, SPG_COLS(2)); break;
-    case 3: SPG_DISPATCH_L(L, SPG_COLS(3)); break;
-    case 4: SPG_DISPATCH_L(L, SPG_COLS(4)); break;
-    default: return hipErrorInvalidValue;
+  const int total = ntiles * nbatch;
+  if (mode < 2) {
+    const dim3 grid(total), block(NT * T);
+    if (nblocks_out) *nblocks_out = total;
+    if (mode == 0) {
+      SPG_DISPATCH_L(L, (k_fft_cols<L_, 0><<<grid, block, 0, st>>>(S, d.P, ntiles, pstride, bstride, tw, NT)));
+    } else {
+      SPG_DISPATCH_L(L, (k_fft_cols<L_, 1><<<grid, block, 0, st>>>(S, d.P, ntiles, pstride, bstride, tw, NT)));
+    }
+    return hipGetLastError();
   }
-#undef SPG_COLS
-  return hipGetLastError();
+#define SPG_ZW(MODE_) \
+  return launch_zw<L_, MODE_>(S, d.P, ntiles, total, pstride, bstride, tw, ws, cs, partials, NT, T, st, nblocks_out)
+  switch (mode) {
+    case 2: SPG_DISPATCH_L(L, SPG_ZW(2)); break;
+    case 3: SPG_DISPATCH_L(L, SPG_ZW(3)); break;
+    case 4: SPG_DISPATCH_L(L, SPG_ZW(4)); break;
+  }
+#undef SPG_ZW
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_dc_nyquist(const Dims& d, float2* S, const float2* tw_z, const float* w0p, const float* wnyq,

@@ -23,7 +23,7 @@ KERNEL_SOURCE = os.path.join(HERE, "csrc", "spg_kernels.hip")
 # kernel-name prefixes (rocprofv3 names) -> kernel classes of the solver
 CLASSES = [
     ("spg::k_fft_cols<512, 0>", "fft_y_fwd"), ("spg::k_fft_cols<512, 1>", "fft_y_inv"),
-    ("spg::k_fft_cols<512, 2>", "fft_z_weight"), ("spg::k_dc_nyquist<512, false>", "dc_nyquist"),
+    ("spg::k_fft_zw<512, 2>", "fft_z_weight"), ("spg::k_dc_nyquist<512, false>", "dc_nyquist"),
     ("spg::k_c2r_x<256", "c2r_x"), ("spg::k_r2c_x<256", "r2c_x"), ("spg::k_prox_tv<", "prox_tv"),
 ]
 
