@@ -50,6 +50,10 @@ def kernel_bytes(shape, storage="compensated"):
         # gradient map in, y' out, x_k in, x_{k+1} out, [x_{k-1} in], [u, v in]
         "prox_tv": lambda momentum, explicit_uv: (rb + rb + xb + xb + (xb if momentum else 0)
                                                   + (2 * rb if explicit_uv else 0)) * n,
+        # fused x transforms: gradient spectrum rows in, spectrum of y' out, x_k in,
+        # x_{k+1} out, [x_{k-1} in], [u, v in]
+        "prox_fft": lambda momentum, explicit_uv: 2 * spec + (xb + xb + (xb if momentum else 0)
+                                                              + (2 * rb if explicit_uv else 0)) * n,
         # check mode: fp32 gradient in, x in, [u, v in]
         "prox_tv_check": lambda explicit_uv: (4 + xb + (2 * rb if explicit_uv else 0)) * n,
         "r2c_x_check": 4 * n + spec,
@@ -57,19 +61,21 @@ def kernel_bytes(shape, storage="compensated"):
     }
 
 
-def schedule_bytes(shape, rounds, iters, steps, storage="compensated"):
-    """Total algorithmic bytes per kernel class over `steps` solves of the schedule."""
+def schedule_bytes(shape, rounds, iters, steps, storage="compensated", fused=False):
+    """Total algorithmic bytes per kernel class over `steps` solves of the schedule (fused:
+    the x-axis transforms of each iteration run inside the stencil/prox kernel)."""
     kb = kernel_bytes(shape, storage)
+    sweeps = ["fft_y_fwd", "fft_z_weight", "dc_nyquist", "fft_y_inv"] + ([] if fused else ["c2r_x", "r2c_x"])
     tot = {k: 0 for k in ["fft_y_fwd", "fft_z_weight", "dc_nyquist", "fft_y_inv", "c2r_x", "prox_tv", "r2c_x"]}
     launches = {k: 0 for k in tot}
     for _ in range(steps):
         for r in range(rounds):
             explicit = r > 0
             for j in range(1, iters + 1):
-                for k in ["fft_y_fwd", "fft_z_weight", "dc_nyquist", "fft_y_inv", "c2r_x", "r2c_x"]:
+                for k in sweeps:
                     tot[k] += kb[k]
                     launches[k] += 1
-                tot["prox_tv"] += kb["prox_tv"](j >= 3, explicit)
+                tot["prox_tv"] += kb["prox_fft" if fused else "prox_tv"](j >= 3, explicit)
                 launches["prox_tv"] += 1
             tot["r2c_x"] += kb["r2c_x"]      # priming transform at the start of each round
             launches["r2c_x"] += 1
@@ -86,8 +92,11 @@ def schedule_bytes(shape, rounds, iters, steps, storage="compensated"):
     return tot, launches
 
 
-def iteration_bytes(shape, explicit_uv=True, storage="compensated"):
+def iteration_bytes(shape, explicit_uv=True, storage="compensated", fused=False):
     kb = kernel_bytes(shape, storage)
+    if fused:
+        return sum(kb[k] for k in ["fft_y_fwd", "fft_z_weight", "dc_nyquist", "fft_y_inv"]) + \
+            kb["prox_fft"](True, explicit_uv)
     return sum(kb[k] for k in ["fft_y_fwd", "fft_z_weight", "dc_nyquist", "fft_y_inv", "c2r_x", "r2c_x"]) + \
         kb["prox_tv"](True, explicit_uv)
 
@@ -220,6 +229,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel HIP events")
     ap.add_argument("--copy-calib", action="store_true", help="only run the copy kernel used to scale HBM counters")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--no-fusion", action="store_true", help="run the x-axis transforms as separate sweeps")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -255,6 +265,9 @@ def main():
     b = torch.from_numpy(vol.b).cuda()
     out = torch.empty(shape, dtype=torch.float32, device="cuda")
     solver = spg.SPGSolver(shape, c["lam"], c["mu"], c["eps"], storage=storage)
+    if args.no_fusion:
+        solver.set_fusion(False)
+    fused = solver.fusion
     rounds, iters = c["rounds"], c["iters"]
     solver.set_data(w, b)
     launch_shape = solver.launch_shape() if args.no_autotune else solver.autotune(3)
@@ -292,7 +305,7 @@ def main():
     elapsed = t1 - t0
     total_iters = rounds * iters * args.steps
     value = total_iters / elapsed
-    it_bytes = iteration_bytes(shape, True, storage)
+    it_bytes = iteration_bytes(shape, True, storage, fused)
     line = {
         "metric": METRIC,
         "value": value,
@@ -314,6 +327,7 @@ def main():
                                        "fp32": "fp32 iterate",
                                        "bf16": "fp32 iterate, bf16 weights and map buffer"}[storage],
                    "step": "set data + solve + fetch map + fp64 objective/KKT check",
+                   "x_transforms": "fused into the stencil/prox kernel" if fused else "separate sweeps",
                    "launch_shape_nt_y_nt_z_zc": list(launch_shape)},
         "ms_per_iteration": 1e3 * elapsed / total_iters,
         "model_bytes_per_iteration": it_bytes,
@@ -322,7 +336,7 @@ def main():
         "final_kkt_rel": result["check"][2],
     }
     if prof is not None:
-        tot_bytes, launches = schedule_bytes(shape, rounds, iters, args.steps, storage)
+        tot_bytes, launches = schedule_bytes(shape, rounds, iters, args.steps, storage, fused)
         kern = {}
         for k, (ms, n) in prof.items():
             if n:
@@ -337,7 +351,8 @@ def main():
         ach = bytes_per_launch / t_avg / 1e9
         traffic = None
         rec = profiling.load(TRAFFIC_RECORD) if (args.config == 3 and storage == "compensated" and
-                                                   not args.iters) else None
+                                                   not args.iters and fused == profiling.record_fused(TRAFFIC_RECORD)) \
+            else None
         if rec and dom in rec["per_launch"]:
             e = rec["per_launch"][dom]
             traffic = e["fetch_bytes"] + e["write_bytes"]

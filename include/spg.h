@@ -168,6 +168,20 @@ spg_status spg_set_launch_shape(spg_problem* P, int32_t nt_y, int32_t nt_z, int3
 spg_status spg_get_launch_shape(const spg_problem* P, int32_t* nt_y, int32_t* nt_z, int32_t* zc);
 spg_status spg_autotune(spg_problem* P, int32_t iters);
 
+/* Fused x-axis transforms (on by default where supported: nx in {64, 128, 256, 512} and
+ * ny a multiple of 4).  An iteration then reads the data gradient as the rows of its
+ * packed x-spectrum and writes the x-spectrum of the next extrapolated map from the
+ * stencil/prox kernel itself, on tiles of 4 full-width rows, instead of running separate
+ * x-axis inverse and forward real FFT sweeps over an fp32 map (16 bytes per voxel less
+ * HBM traffic per iteration).  The iterates agree with the unfused path to rounding (the
+ * same operations; the prox of the compensated mode is fp64 in both).  With
+ * SPG_FLAG_BF16_STORAGE the fused path keeps the gradient and extrapolated rows in fp32.
+ * spg_set_fusion(P, 1) on a grid without support returns SPG_E_UNSUPPORTED; 0 selects
+ * the separate sweeps.  Iterations of spg_run_checkpointed always use the separate sweeps
+ * (they keep the data gradient of every iteration). */
+spg_status spg_set_fusion(spg_problem* P, int32_t enable);
+spg_status spg_get_fusion(const spg_problem* P, int32_t* enabled);
+
 /* Batches: independent problems of any sizes (gold-standard half-maps, class volumes)
  * advanced together in one HIP graph.  spg_batch_create takes n (1..64) distinct problems
  * and the caller's stream (hipStream_t, NULL = default), which waits for every graph; it

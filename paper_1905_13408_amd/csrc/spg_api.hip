@@ -143,6 +143,7 @@ struct spg_problem {
   // launch shapes (chosen by spg_autotune): columns per tile of the y and z passes, z-slab
   // depth of the stencil kernel
   int nt_y = 16, nt_z = 16, zc = PT_ZC;
+  bool fused = false;  // fused x-axis transforms in the stencil/prox kernel
   // unrolled solve recorded by spg_run_checkpointed for spg_vjp
   bool vjp_valid = false;
   int32_t vjp_K = 0, vjp_C = 0;
@@ -233,10 +234,11 @@ spg_status read_results(spg_problem* P, double* host, int n) {
   return SPG_OK;
 }
 
-// Forward FFT of the x-axis rows of rbuf (already holding y) followed by the y, z
-// passes with the weight step, the y inverse and the x inverse into rbuf.  obj: also
-// collect the data-term partials.
-spg_status gradient_pipeline(spg_problem* P, bool obj, int* nA, int* nB, void* gout, bool gout_bf16) {
+// The y, z passes with the weight step on the x-spectrum rows in S (the forward x
+// transform of y already done), the y inverse and, unless x_inverse is false, the x
+// inverse into gout.  obj: also collect the data-term partials.
+spg_status gradient_pipeline(spg_problem* P, bool obj, int* nA, int* nB, void* gout, bool gout_bf16,
+                             bool x_inverse = true) {
   const Dims& d = P->d;
   hipStream_t st = P->stream;
   const float2* twy = P->at<float2>(P->lay.tw_y);
@@ -259,6 +261,7 @@ spg_status gradient_pipeline(spg_problem* P, bool obj, int* nA, int* nB, void* g
   prof_begin(P, SPG_KERNEL_FFT_Y_INV);
   SPG_CK(P, launch_fft_cols(d, P->S(), 1, 1, twy, nullptr, nullptr, nullptr, st, nullptr, P->nt_y));
   prof_end(P, SPG_KERNEL_FFT_Y_INV);
+  if (!x_inverse) return SPG_OK;
   prof_begin(P, SPG_KERNEL_C2R_X);
   SPG_CK(P, launch_c2r_x(d, P->S(), gout, gout_bf16, P->at<float2>(P->lay.tw_m), P->at<float2>(P->lay.tw_n), st));
   prof_end(P, SPG_KERNEL_C2R_X);
@@ -353,6 +356,7 @@ spg_status spg_create(const spg_params* p, void* d_workspace, size_t bytes, void
   P->comp = (p->flags & SPG_FLAG_COMPENSATED) != 0;
   P->store = P->comp ? ST_COMP : ((p->flags & SPG_FLAG_BF16_STORAGE) ? ST_BF16 : ST_PLAIN);
   P->dn2 = dnorm2_of(p->nx, p->ny, p->nz);
+  P->fused = prox_fft_supported(P->d);
 
   // Twiddle tables exp(-2 pi i m / n), computed in fp64 and rounded once.
   const int lens[4] = {p->nx / 2, p->nx, p->ny, p->nz};
@@ -497,7 +501,8 @@ static spg_status iterate_once(spg_problem* P, float* capture_g) {
       if ((s = r2c(P, P->rbuf(), P->bf()))) return s;
       P->primed = true;
     }
-    if ((s = gradient_pipeline(P, false, nullptr, nullptr, P->rbuf(), P->bf()))) return s;
+    const bool fuse = P->fused && !capture_g;
+    if ((s = gradient_pipeline(P, false, nullptr, nullptr, P->rbuf(), P->bf(), !fuse))) return s;
     if (capture_g)
       SPG_CK(P, hipMemcpyAsync(capture_g, P->rbuf(), (size_t)d.nvox * 4, hipMemcpyDeviceToDevice, P->stream));
     const double t_next = P->prm.accel ? 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * P->t * P->t)) : 1.0;
@@ -505,9 +510,14 @@ static spg_status iterate_once(spg_problem* P, float* capture_g) {
     const int nxt = 3 - P->cur - P->old;
     ProxArgs a = prox_args(P, nxt, P->m_cur, m_next);
     prof_begin(P, SPG_KERNEL_PROX_TV);
-    SPG_CK(P, launch_prox_tv(d, a, P->store, false, P->stream));
+    if (fuse) {
+      SPG_CK(P, launch_prox_fft(d, a, P->S(), P->at<float2>(P->lay.tw_m), P->at<float2>(P->lay.tw_n), P->store,
+                                P->stream));
+    } else {
+      SPG_CK(P, launch_prox_tv(d, a, P->store, false, P->stream));
+    }
     prof_end(P, SPG_KERNEL_PROX_TV);
-    if ((s = r2c(P, P->rbuf(), P->bf()))) return s;
+    if (!fuse && (s = r2c(P, P->rbuf(), P->bf()))) return s;
     P->old = P->cur;
     P->cur = nxt;
     P->t = t_next;
@@ -730,6 +740,21 @@ spg_status spg_set_launch_shape(spg_problem* P, int32_t nt_y, int32_t nt_z, int3
   P->nt_y = nt_y;
   P->nt_z = nt_z;
   P->zc = zc;
+  return SPG_OK;
+}
+
+spg_status spg_set_fusion(spg_problem* P, int32_t enable) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if (enable && !prox_fft_supported(P->d))
+    return set_err(P, SPG_E_UNSUPPORTED, "fused x transforms need nx in {64, 128, 256, 512} and ny % 4 == 0");
+  P->fused = enable != 0;
+  return SPG_OK;
+}
+
+spg_status spg_get_fusion(const spg_problem* P, int32_t* enabled) {
+  if (!P || !enabled) return SPG_E_INVAL;
+  *enabled = P->fused ? 1 : 0;
   return SPG_OK;
 }
 

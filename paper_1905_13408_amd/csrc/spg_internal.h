@@ -56,6 +56,14 @@ struct ProxArgs {
 
 int prox_num_blocks(const Dims& d, int zc);
 
+// Fused x-axis transforms + stencil/prox on full-width rows: reads the gradient as the
+// packed x-spectrum rows in S (after the y and z passes), writes x_{k+1} and the
+// x-spectrum of y_{k+1} back into S.  Grids with nx in {64, 128, 256, 512} and ny a
+// multiple of 8.
+bool prox_fft_supported(const Dims& d);
+hipError_t launch_prox_fft(const Dims& d, const ProxArgs& a, float2* S, const float2* tw_m, const float2* tw_n,
+                           int store, hipStream_t st);
+
 hipError_t launch_fft_cols(const Dims& d, float2* S, int axis /*1 = y, 2 = z*/, int mode,
                            const float2* tw, const float* ws, const float2* cs, double* partials,
                            hipStream_t st, int* nblocks_out, int nt = 16 /* columns per tile: 8 or 16 */);

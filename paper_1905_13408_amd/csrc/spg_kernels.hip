@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "spg_internal.h"
 
 namespace spg {
@@ -284,9 +286,12 @@ struct RegPlan {
   }
 };
 
+// act = false: the thread takes part in the barriers only (blocks whose threads do not all
+// hold a transform).
 template <int L, int TT, int S, bool INV>
 __device__ __forceinline__ void reg_stage(float2 (&a)[reg_e(L, TT)], float* __restrict__ re,
-                                          float* __restrict__ im, int ps, int q, const float2* __restrict__ twl) {
+                                          float* __restrict__ im, int ps, int q, const float2* __restrict__ twl,
+                                          bool act = true) {
   using P = RegPlan<L, TT>;
   constexpr int R = P::radix(S);
   constexpr int Ns = P::span(S);
@@ -296,21 +301,24 @@ __device__ __forceinline__ void reg_stage(float2 (&a)[reg_e(L, TT)], float* __re
   constexpr bool first = S == 0;
   constexpr bool last = S == P::ns - 1;
   float2 v[NB][R];
+  if (act) {
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
+    for (int b = 0; b < NB; ++b) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if constexpr (first) {
-        v[b][r] = a[b + r * (STR / T)];
-      } else {
-        const int idx = (q + T * b + r * STR) * ps;
-        v[b][r] = make_float2(re[idx], im[idx]);
+      for (int r = 0; r < R; ++r) {
+        if constexpr (first) {
+          v[b][r] = a[b + r * (STR / T)];
+        } else {
+          const int idx = (q + T * b + r * STR) * ps;
+          v[b][r] = make_float2(re[idx], im[idx]);
+        }
       }
     }
   }
   if constexpr (!first && !last) __syncthreads();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
+    if (!act) break;
     const int j = q + T * b;
     const int k = j % Ns;
     if constexpr (Ns > 1) {
@@ -342,10 +350,10 @@ __device__ __forceinline__ void reg_stage(float2 (&a)[reg_e(L, TT)], float* __re
 
 template <int L, int TT, int S, bool INV, int SEND = RegPlan<L, TT>::ns>
 __device__ __forceinline__ void reg_stages(float2 (&a)[reg_e(L, TT)], float* re, float* im, int ps, int q,
-                                           const float2* twl) {
+                                           const float2* twl, bool act = true) {
   if constexpr (S < SEND) {
-    reg_stage<L, TT, S, INV>(a, re, im, ps, q, twl);
-    reg_stages<L, TT, S + 1, INV, SEND>(a, re, im, ps, q, twl);
+    reg_stage<L, TT, S, INV>(a, re, im, ps, q, twl, act);
+    reg_stages<L, TT, S + 1, INV, SEND>(a, re, im, ps, q, twl, act);
   }
 }
 
@@ -353,8 +361,8 @@ __device__ __forceinline__ void reg_stages(float2 (&a)[reg_e(L, TT)], float* re,
 // LDS data planes (barrier after their last use) and the twiddle table is visible.
 template <int L, bool INV, int TT = FftPlan<L>::T>
 __device__ __forceinline__ void fft_reg(float2 (&a)[reg_e(L, TT)], float* re, float* im, int ps, int q,
-                                        const float2* twl) {
-  reg_stages<L, TT, 0, INV>(a, re, im, ps, q, twl);
+                                        const float2* twl, bool act = true) {
+  reg_stages<L, TT, 0, INV>(a, re, im, ps, q, twl, act);
 }
 
 // Threads per column of the column passes: more threads for the long axes keep the
@@ -1088,6 +1096,352 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
   }
 }
 
+// ---------------------------------------------------------------- fused x transforms + stencil/prox
+// One SPG step on full-width tiles: NX (= nx) x-columns by PF_TY y-rows, marched along z
+// over a slab of a.zc planes.  The data gradient of a plane comes in as the rows of its
+// packed x-spectrum (after the y and z passes) and is turned into real rows here (the
+// x-axis inverse real FFT); y_{k+1} of the plane goes out as the x-spectrum of its rows
+// (the x-axis forward real FFT of the next iteration).  The stencil needs no x halo:
+// rows wrap inside the tile.  Per plane, LDS holds y on three planes (z-1, z, z+1) with
+// one halo row on each side, and sc = v / max(eps, |Dy|) on two planes (z, z+1) with
+// the row below the tile; the p = sc Dy terms of D^T p are formed from these rings.
+// Thread (x = tid % NX, r = tid / NX) owns rows r + 2h (h < PF_TY/2) and halo row -1
+// (r = 0) or PF_TY (r = 1); the next plane's words are prefetched one step ahead.
+// The row transforms are batched over PF_KB planes: the gradient rows of a batch sit in
+// LDS while its planes are stepped (each plane's y_{k+1} rows replace its gradient rows),
+// then one transform phase on all threads takes the batch's y_{k+1} rows forward into S
+// (threads [0, R)) while the other half inverts the next batch's gradient rows, as the
+// conjugate of the forward transform of the conjugate (threads [R, 2R), R = PF_KB*PF_TY
+// rows of FT threads).  The arithmetic of every output is that of k_c2r_x, k_prox_tv and
+// k_r2c_x in sequence, except that with bf16 storage the gradient and y_{k+1} rows stay
+// fp32 (they never reach HBM here).
+constexpr int PF_TY = 4;
+constexpr int PF_KB = 4;
+
+template <int M>
+struct PfT {  // threads per row of the M-point complex transforms
+  static constexpr int T = largest_divisor_le(plan_gcd(M), 32);
+  static constexpr int E = M / T;
+};
+
+// PRIOR: the gamma term's previous map is given (else it is 0).
+template <int NX, int ST, bool PRIOR>
+__global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restrict__ S,
+                                                     const float2* __restrict__ twm,
+                                                     const float2* __restrict__ twn, int nty) {
+  constexpr bool COMP = ST == ST_COMP;
+  constexpr bool BF = ST == ST_BF16;
+  constexpr int TY = PF_TY, KB = PF_KB;
+  constexpr int M = NX / 2;
+  constexpr int FT = PfT<M>::T, FE = PfT<M>::E;
+  constexpr int NR = KB * TY;  // rows of one batch
+  using VT = typename std::conditional<BF, uint16_t, float>::type;  // penalty-weight word
+  constexpr int NO = TY / 2;  // own rows per thread
+  static_assert(TY % 2 == 0 && 2 * NR * FT == 2 * NX, "one transform row share per thread");
+  __shared__ float sY[3][TY + 2][NX];
+  __shared__ float sSC[2][TY + 1][NX];
+  __shared__ float sG[KB][TY][NX];  // gradient rows of the batch, then its y_{k+1} rows
+  __shared__ float sFre[2 * NR][M + 1];
+  __shared__ float sFim[2 * NR][M + 1];
+  __shared__ float2 s_tw[M];   // M-point transform twiddles
+  __shared__ float2 s_twn[M];  // W^k of the real-row pre- and post-processing
+
+  const int tid = threadIdx.x;
+  int x = tid % NX, r = tid / NX;
+  int xm = (x + NX - 1) % NX, xp = (x + 1) % NX;
+  const int by = blockIdx.x % nty;
+  const int bz = blockIdx.x / nty;
+  const int ny = a.ny, nz = a.nz;
+  const int y0 = by * TY;
+  const int z0 = bz * a.zc;
+  const int z1 = min(z0 + a.zc, nz);
+  const long long plane = (long long)NX * ny;
+  // In-plane element offsets (below 2^18): own rows ly = r + 2h (inside the grid, as ny is
+  // a multiple of TY) and the halo row; global accesses take a block-uniform plane base
+  // and these offsets scaled to bytes.
+  unsigned own_off[NO];
+#pragma unroll
+  for (int h = 0; h < NO; ++h) own_off[h] = (unsigned)((y0 + r + 2 * h) * NX + x);
+  const int hly = r == 0 ? -1 : TY;
+  unsigned halo_off = (unsigned)((((y0 + hly) % ny + ny) % ny) * NX + x);
+  // transform role: thread row fr in [0, 2 NR): rows [0, NR) forward (y_{k+1} of the
+  // current batch, row fr = plane-in-batch * TY + tile row), rows [NR, 2 NR) inverse (the
+  // gradient of the next batch, same numbering)
+  int fr = tid / FT, fq = tid % FT;
+
+  auto slot3 = [](int zz) { return ((zz % 3) + 3) % 3; };
+  auto pz_of = [&](int zz) { return (long long)(zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz)) * plane; };
+  auto fetch_one = [&](long long pz, unsigned o, RawX& w) {
+    w.xh = ld_at(a.xk_hi + pz, o * 4u);
+    if constexpr (COMP) w.xl = ld_at(a.xk_lo + pz, o * 2u);
+    if (a.read_old) {
+      w.oh = ld_at(a.xo_hi + pz, o * 4u);
+      if constexpr (COMP) w.ol = ld_at(a.xo_lo + pz, o * 2u);
+    }
+  };
+  auto ld_w = [&](const void* base, long long pz, unsigned o) -> float {
+    const VT* b = reinterpret_cast<const VT*>(base) + pz;
+    if constexpr (BF) return bf16_to_f32(ld_at(b, o * 2u));
+    else return ld_at(b, o * 4u);
+  };
+  auto fetch_plane = [&](int zz, RawX* own, RawX& halo, float* vv) {
+    const long long pz = pz_of(zz);
+#pragma unroll
+    for (int h = 0; h < NO; ++h) fetch_one(pz, own_off[h], own[h]);
+    fetch_one(pz, halo_off, halo);
+    if (a.v) {
+#pragma unroll
+      for (int h = 0; h < NO; ++h) vv[h] = ld_w(a.v, pz, own_off[h]);
+      vv[NO] = r == 1 ? ld_w(a.v, pz, halo_off) : 1.0f;
+    } else {
+#pragma unroll
+      for (int h = 0; h <= NO; ++h) vv[h] = 1.0f;
+    }
+  };
+  auto fetch_out = [&](int zz, float* uu, float* xq) {
+    const long long pz = (long long)zz * plane;
+#pragma unroll
+    for (int h = 0; h < NO; ++h) {
+      uu[h] = a.u ? ld_w(a.u, pz, own_off[h]) : 1.0f;
+      if constexpr (PRIOR) xq[h] = ld_at(a.xprev + pz, own_off[h] * 4u);
+      else xq[h] = 0.f;
+    }
+  };
+  // spectrum rows of the batch starting at plane zb for the inverse half (row fr - NR)
+  auto fetch_spec = [&](int zb, float2* sr) {
+    const int zz = zb + (fr - NR) / TY;
+    if (fr >= NR && zz < z1) {
+      const float2* __restrict__ src = S + ((long long)zz * ny + y0 + (fr - NR) % TY) * M;
+#pragma unroll
+      for (int i = 0; i < FE; ++i) sr[i] = ld_at(src, (unsigned)(fq + FT * i) * 8u);
+    }
+  };
+  // y of a plane into the ring; own y (fp64 in the compensated mode) and x_k kept
+  auto store_plane = [&](int zz, const RawX* own, const RawX& halo, double* ys, double* xks) {
+    float(*Y)[NX] = sY[slot3(zz)];
+#pragma unroll
+    for (int h = 0; h < NO; ++h) {
+      double yv, xv;
+      eval_raw<COMP>(a, own[h], yv, xv);
+      ys[h] = yv;
+      xks[h] = xv;
+      Y[r + 2 * h + 1][x] = (float)yv;
+    }
+    double yv, xv;
+    eval_raw<COMP>(a, halo, yv, xv);
+    Y[hly + 1][x] = (float)yv;
+  };
+  // sc = v / max(eps, |Dy|) at row ly of plane zz, column x (backward differences)
+  auto sc_at = [&](int zz, int ly, float vv) {
+    const float(*Y)[NX] = sY[slot3(zz)];
+    const float(*Yp)[NX] = sY[slot3(zz - 1)];
+    const float yc = Y[ly + 1][x];
+    const float dxv = yc - Y[ly + 1][xm];
+    const float dyv = yc - Y[ly][x];
+    const float dzv = yc - Yp[ly + 1][x];
+    const float n2 = dxv * dxv + dyv * dyv + dzv * dzv;
+    const float inv = n2 > a.eps * a.eps ? rsqrtf(n2) : 1.0f / a.eps;
+    return vv * inv;
+  };
+  auto compute_sc = [&](int zz, const float* vv) {
+    float(*SC)[NX] = sSC[zz & 1];
+#pragma unroll
+    for (int h = 0; h < NO; ++h) SC[r + 2 * h][x] = sc_at(zz, r + 2 * h, vv[h]);
+    if (r == 1) SC[TY][x] = sc_at(zz, TY, vv[NO]);
+  };
+  // One transform phase.  Forward half (fr < NR): the y_{k+1} rows of the batch at plane
+  // zf (planes < zf_end) from sG into S.  Inverse half: the spectrum rows in `sa` of the
+  // batch at plane zi (planes < z1) into sG, real rows.  Either batch may be empty.
+  auto transform_phase = [&](int zf, int zf_end, int zi, float2* sa) {
+    const bool fwd = fr < NR;
+    const int row = fwd ? fr : fr - NR;
+    const int zz = (fwd ? zf : zi) + row / TY;
+    const bool act = fwd ? zz < zf_end : zz < z1;
+    float* fre = &sFre[fr][0];
+    float* fim = &sFim[fr][0];
+    float(*G)[NX] = sG[row / TY];
+    float2 v[FE];
+    if (act) {
+      if (fwd) {
+#pragma unroll
+        for (int i = 0; i < FE; ++i) v[i] = *reinterpret_cast<const float2*>(&G[row % TY][2 * (fq + FT * i)]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < FE; ++i) {
+          fre[fq + FT * i] = sa[i].x;
+          fim[fq + FT * i] = sa[i].y;
+        }
+      }
+    }
+    __syncthreads();
+    // inverse half: Z[k] = E + i O from the row and its mirror (as k_c2r_x), conjugated
+    if (act && !fwd) {
+#pragma unroll
+      for (int i = 0; i < FE; ++i) {
+        const int k = fq + FT * i;
+        const float2 xk = sa[i];
+        float2 zk;
+        if (k == 0) {
+          zk = make_float2(xk.x + xk.y, xk.x - xk.y);
+        } else {
+          const float2 xmr = make_float2(fre[M - k], fim[M - k]);
+          const float2 e = make_float2(xk.x + xmr.x, xk.y - xmr.y);
+          const float2 d = make_float2(xk.x - xmr.x, xk.y + xmr.y);
+          const float2 o = cmulc(d, s_twn[k]);
+          zk = make_float2(e.x - o.y, e.y + o.x);
+        }
+        v[i] = make_float2(zk.x, -zk.y);
+      }
+    }
+    __syncthreads();
+    fft_reg<M, false, FT>(v, fre, fim, 1, fq, s_tw, act);
+    if (act && !fwd) {  // z = conj(FFT(conj Z)): interleaved real samples of the row
+#pragma unroll
+      for (int i = 0; i < FE; ++i)
+        *reinterpret_cast<float2*>(&G[row % TY][2 * (fq + FT * i)]) = make_float2(v[i].x, -v[i].y);
+    }
+    __syncthreads();
+    // forward half: X[k] from Z[k] and Z[M-k] (as k_r2c_x) into the spectrum rows
+    if (act && fwd) {
+#pragma unroll
+      for (int i = 0; i < FE; ++i) {
+        fre[fq + FT * i] = v[i].x;
+        fim[fq + FT * i] = v[i].y;
+      }
+    }
+    __syncthreads();
+    if (act && fwd) {
+      float2* __restrict__ dst = S + ((long long)zz * ny + y0 + row % TY) * M;
+#pragma unroll
+      for (int i = 0; i < FE; ++i) {
+        const int k = fq + FT * i;
+        const float2 zk = v[i];
+        float2 out;
+        if (k == 0) {
+          out = make_float2(zk.x + zk.y, zk.x - zk.y);
+        } else {
+          const float2 zm = make_float2(fre[M - k], fim[M - k]);
+          const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+          const float2 d = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y + zm.y));
+          const float2 o = make_float2(d.y, -d.x);
+          out = cadd(e, cmul(s_twn[k], o));
+        }
+        st_at(dst, (unsigned)k * 8u, out);
+      }
+    }
+  };
+
+  for (int i = tid; i < M; i += blockDim.x) {
+    s_tw[i] = twm[i];
+    s_twn[i] = twn[i];
+  }
+  // ---- prologue: the gradient rows of the first batch; y on planes z0-1, z0; sc(z0);
+  // prefetch plane z0+1, the outputs' inputs of plane z0 and the next batch's spectrum
+  RawX rown[NO], rhalo;
+  float rv[NO + 1];
+  double own_y[NO], own_xk[NO], nxt_y[NO], nxt_xk[NO];
+  float u_cur[NO], xq_cur[NO];
+  float2 sa[FE];
+  fetch_spec(z0, sa);
+  {
+    double d1[NO], d2[NO];
+    fetch_plane(z0 - 1, rown, rhalo, rv);
+    store_plane(z0 - 1, rown, rhalo, d1, d2);
+    fetch_plane(z0, rown, rhalo, rv);
+    store_plane(z0, rown, rhalo, own_y, own_xk);
+  }
+  transform_phase(z0, z0, z0, sa);  // inverse half only; ends with a barrier
+  compute_sc(z0, rv);
+  fetch_plane(z0 + 1, rown, rhalo, rv);
+  fetch_out(z0, u_cur, xq_cur);
+  fetch_spec(z0 + KB, sa);
+
+  for (int zb = z0; zb < z1; zb += KB) {
+    const int zb_end = min(zb + KB, z1);
+    for (int z = zb; z < zb_end; ++z) {
+      // The lane indices pass through empty asm statements so that the LDS and global
+      // addresses derived from them are formed inside the loop where they are used, not
+      // hoisted out of it and held in registers across all planes.
+      asm volatile("" : "+v"(x), "+v"(r), "+v"(xm), "+v"(xp), "+v"(halo_off));
+#pragma unroll
+      for (int h = 0; h < NO; ++h) asm volatile("" : "+v"(own_off[h]));
+      asm volatile("" : "+v"(fr), "+v"(fq));
+      // y of plane z+1 from the words fetched during the previous step
+      store_plane(z + 1, rown, rhalo, nxt_y, nxt_xk);
+      __syncthreads();
+      compute_sc(z + 1, rv);
+      if (z + 1 < z1) fetch_plane(z + 2, rown, rhalo, rv);  // in flight until the next step
+      __syncthreads();
+      // ---- outputs of plane z (as k_prox_tv)
+      {
+        const float(*Ym)[NX] = sY[slot3(z - 1)];
+        const float(*Y0)[NX] = sY[slot3(z)];
+        const float(*Y1)[NX] = sY[slot3(z + 1)];
+        const float(*SC0)[NX] = sSC[z & 1];
+        const float(*SC1)[NX] = sSC[(z + 1) & 1];
+        float(*G)[NX] = sG[z - zb];
+        const long long pz = (long long)z * plane;
+        float* __restrict__ xnh = a.xn_hi + pz;
+        uint16_t* __restrict__ xnl = a.xn_lo + pz;
+#pragma unroll
+        for (int h = 0; h < NO; ++h) {
+          const int ly = r + 2 * h;
+          const float yc = Y0[ly + 1][x];
+          const float sc = SC0[ly][x];
+          // p = sc Dy rounded as stored fp32 values, summed in the order z, y, x, -x+, -y+, -z+
+          const float pzc = __fmul_rn(sc, yc - Ym[ly + 1][x]);
+          const float pyc = __fmul_rn(sc, yc - Y0[ly][x]);
+          const float pxc = __fmul_rn(sc, yc - Y0[ly + 1][xm]);
+          const float pxn = __fmul_rn(SC0[ly][xp], Y0[ly + 1][xp] - yc);
+          const float pyn = __fmul_rn(SC0[ly + 1][x], Y0[ly + 2][x] - yc);
+          const float pzn = __fmul_rn(SC1[ly][x], Y1[ly + 1][x] - yc);
+          const float gtv = pzc + pyc + pxc - pxn - pyn - pzn;
+          const float gd = G[ly][x];
+          const float uu = u_cur[h];
+          const float xq = xq_cur[h];
+          float ynext;
+          if constexpr (COMP) {
+            const double y = own_y[h];
+            const double dprior = y - (double)xq;
+            const double zv = y - a.lr * ((double)gd + a.mu * (double)gtv + 2.0 * a.gamma * dprior);
+            const double t = a.lr * a.lam * (double)uu;
+            const double az = fabs(zv) - t;
+            const double xn = az > 0.0 ? copysign(az, zv) : 0.0;
+            const float hi = (float)xn;
+            const uint16_t lo = f32_to_bf16((float)(xn - (double)hi));
+            st_at(xnh, own_off[h] * 4u, hi);
+            st_at(xnl, own_off[h] * 2u, lo);
+            const double xs = (double)hi + (double)bf16_to_f32(lo);
+            ynext = (float)(xs + a.m_next * (xs - own_xk[h]));
+          } else {
+            const float y = (float)own_y[h];
+            const float dprior = y - xq;
+            const float zv = y - (float)a.lr * (gd + (float)a.mu * gtv + 2.0f * (float)a.gamma * dprior);
+            const float t = (float)a.lr * (float)a.lam * uu;
+            const float az = fabsf(zv) - t;
+            const float xn = az > 0.f ? copysignf(az, zv) : 0.f;
+            st_at(xnh, own_off[h] * 4u, xn);
+            const float xk = (float)own_xk[h];
+            ynext = xn + (float)a.m_next * (xn - xk);
+          }
+          G[ly][x] = ynext;
+        }
+      }
+      if (z + 1 < z1) fetch_out(z + 1, u_cur, xq_cur);
+#pragma unroll
+      for (int h = 0; h < NO; ++h) {
+        own_y[h] = nxt_y[h];
+        own_xk[h] = nxt_xk[h];
+      }
+      __syncthreads();  // sY slot z-1 and the sG rows are rewritten next
+    }
+    // ---- the batch's y_{k+1} rows into S; the next batch's gradient rows into sG
+    transform_phase(zb, zb_end, zb + KB, sa);
+    fetch_spec(zb + 2 * KB, sa);
+    __syncthreads();  // the exchange rows are rewritten by the next phase
+  }
+}
+
 // ---------------------------------------------------------------- elementwise kernels
 
 // y = x_k + m (x_k - x_{k-1}) into the map buffer (the first x-axis transform of a round).
@@ -1718,6 +2072,37 @@ static dim3 ew_grid(long long n) {
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
   return dim3((unsigned)g);
+}
+
+bool prox_fft_supported(const Dims& d) {
+  return (d.nx == 64 || d.nx == 128 || d.nx == 256 || d.nx == 512) && d.ny >= PF_TY && d.ny % PF_TY == 0;
+}
+
+hipError_t launch_prox_fft(const Dims& d, const ProxArgs& a, float2* S, const float2* tw_m, const float2* tw_n,
+                           int store, hipStream_t st) {
+  if (!prox_fft_supported(d) || a.zc < 1 || store < ST_PLAIN || store > ST_BF16) return hipErrorInvalidValue;
+  const int nty = d.ny / PF_TY;
+  const long long nblk = (long long)nty * ((d.nz + a.zc - 1) / a.zc);
+  if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)nblk), block(2 * d.nx);
+#define SPG_PF2(NX_, ST_)                                                             \
+  if (a.xprev) k_prox_fft<NX_, ST_, true><<<grid, block, 0, st>>>(a, S, tw_m, tw_n, nty); \
+  else k_prox_fft<NX_, ST_, false><<<grid, block, 0, st>>>(a, S, tw_m, tw_n, nty);
+#define SPG_PF(NX_)                                   \
+  switch (store) {                                    \
+    case ST_PLAIN: SPG_PF2(NX_, ST_PLAIN); break;     \
+    case ST_COMP: SPG_PF2(NX_, ST_COMP); break;       \
+    default: SPG_PF2(NX_, ST_BF16); break;            \
+  }
+  switch (d.nx) {
+    case 64: SPG_PF(64); break;
+    case 128: SPG_PF(128); break;
+    case 256: SPG_PF(256); break;
+    default: SPG_PF(512); break;
+  }
+#undef SPG_PF
+#undef SPG_PF2
+  return hipGetLastError();
 }
 
 hipError_t launch_prime(const Dims& d, void* rbuf, const float* xk_hi, const uint16_t* xk_lo, const float* xo_hi,

@@ -28,6 +28,9 @@ CLASSES = [
 ]
 
 
+FUSED = "spg::k_prox_fft<"  # stencil/prox kernel with the x-axis transforms inside
+
+
 def source_sha256(path: str = KERNEL_SOURCE) -> str:
     with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
@@ -56,14 +59,20 @@ def summarize(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, 
     for prefix, cls in CLASSES:
         fv = [v for k, lst in fa.items() if k.startswith(prefix) and "true>" not in k[len(prefix):] for v in lst]
         wv = [v for k, lst in wa.items() if k.startswith(prefix) and "true>" not in k[len(prefix):] for v in lst]
-        if cls == "prox_tv":  # iteration launches only (the check launch is another instance)
-            fv = [v for k, lst in fa.items() if k.startswith(prefix) and k.endswith("false>") for v in lst]
-            wv = [v for k, lst in wa.items() if k.startswith(prefix) and k.endswith("false>") for v in lst]
+        if cls == "prox_tv":
+            # iteration launches only: the fused kernel where it ran, else the stencil kernel
+            # outside its check mode (another instance)
+            fv = [v for k, lst in fa.items() if k.startswith(FUSED) for v in lst]
+            wv = [v for k, lst in wa.items() if k.startswith(FUSED) for v in lst]
+            if not fv:
+                fv = [v for k, lst in fa.items() if k.startswith(prefix) and k.endswith("false>") for v in lst]
+                wv = [v for k, lst in wa.items() if k.startswith(prefix) and k.endswith("false>") for v in lst]
         if fv and wv:
             out[cls] = {"launches": len(fv), "fetch_bytes": fs * sum(fv) / len(fv),
                         "write_bytes": wsc * sum(wv) / len(wv)}
+    fused = any(k.startswith(FUSED) for k in fa)
     return {"command": command, "kernel_source_sha256": source_sha256(), "fetch_scale": fs, "write_scale": wsc,
-            "copy_bytes_each_way": copy_bytes, "per_launch": out}
+            "copy_bytes_each_way": copy_bytes, "fused_x_transforms": fused, "per_launch": out}
 
 
 def load(path):
@@ -75,6 +84,12 @@ def load(path):
     if rec.get("kernel_source_sha256") != source_sha256():
         return None
     return rec
+
+
+def record_fused(path) -> bool:
+    """Whether the record at `path` was taken with the fused x-transform kernel."""
+    rec = load(path)
+    return bool(rec and rec.get("fused_x_transforms", False))
 
 
 if __name__ == "__main__":

@@ -74,6 +74,8 @@ def lib() -> ctypes.CDLL:
         "spg_profile_end": [P, POINTER(c_double), POINTER(c_int32)],
         "spg_set_launch_shape": [P, c_int32, c_int32, c_int32],
         "spg_get_launch_shape": [P, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)],
+        "spg_set_fusion": [P, c_int32],
+        "spg_get_fusion": [P, POINTER(c_int32)],
         "spg_autotune": [P, c_int32],
         "spg_batch_create": [POINTER(P), c_int32, P, POINTER(P)],
         "spg_batch_run": [P, c_int32],
@@ -271,6 +273,17 @@ class SPGSolver:
 
     def set_launch_shape(self, nt_y, nt_z, zc):
         self._check(self._L.spg_set_launch_shape(self._h, int(nt_y), int(nt_z), int(zc)))
+
+    @property
+    def fusion(self) -> bool:
+        """Whether iterations run the x-axis transforms inside the stencil/prox kernel."""
+        v = c_int32()
+        self._check(self._L.spg_get_fusion(self._h, byref(v)))
+        return bool(v.value)
+
+    def set_fusion(self, enable: bool):
+        """Select the fused x-transform path (raises where the grid has no support)."""
+        self._check(self._L.spg_set_fusion(self._h, 1 if enable else 0))
 
     # ------------------------------------------------------------------ reverse mode
     def run_checkpointed(self, K: int, C: int):

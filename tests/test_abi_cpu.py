@@ -46,7 +46,6 @@ def test_workspace_size_model():
     nz, ny, nx = 64, 32, 16
     n = nx * ny * nz
     b = _ws((nz, ny, nx))
-    # 3 fp32 + 3 bf16 iterate slots, u, v, spectrum, gradient map, folded weights and data
     # 3 fp32 + 3 bf16 iterate slots, u, v, spectrum, map buffer, prior map, folded weights and data
     core = 3 * 4 * n + 3 * 2 * n + 2 * 4 * n + 4 * n + 4 * n + 4 * n + 2 * n + 4 * n
     assert core <= b <= core + 2 * 1024 * 1024
@@ -104,6 +103,9 @@ def test_null_handles_are_rejected(L):
     assert L.spg_set_map(None, None) == -1
     assert L.spg_reweight(None, 0.1, 0.1) == -1
     assert L.spg_final_check(None, None, None, None) == -1
+    assert L.spg_set_fusion(None, 1) == -1
+    on = ctypes.c_int32(7)
+    assert L.spg_get_fusion(None, ctypes.byref(on)) == -1 and on.value == 7
     assert b"NULL" in L.spg_last_error(None)
 
 
