@@ -174,7 +174,7 @@ def bench_batch(args):
     for shape, vol, lam, mu in members:
         sv = spg.SPGSolver(shape, lam, mu, 1e-3, storage=args.storage)
         sv.set_data(torch.from_numpy(vol.w).cuda(), torch.from_numpy(vol.b).cuda())
-        shapes_tuned.append(sv.autotune(3) if not args.no_autotune else sv.launch_shape())
+        shapes_tuned.append(list(sv.autotune(3) if not args.no_autotune else sv.launch_shape()) + [sv.fusion])
         solvers.append(sv)
     batch = spg.SPGBatch(solvers)
     vox_it = sum(int(sh[0]) ** 3 for sh, _, _, _ in members) * iters
@@ -210,7 +210,7 @@ def bench_batch(args):
         "voxel_iterations_per_s": vox_it / res["graph"],
         "eager_ms_per_step": 1e3 * res["eager"],
         "graph_speedup_vs_eager": res["eager"] / res["graph"],
-        "launch_shapes": shapes_tuned,
+        "launch_shapes_nt_y_nt_z_zc_fused": shapes_tuned,
     }
     print(json.dumps(line))
     batch.close()
@@ -267,11 +267,14 @@ def main():
     solver = spg.SPGSolver(shape, c["lam"], c["mu"], c["eps"], storage=storage)
     if args.no_fusion:
         solver.set_fusion(False)
-    fused = solver.fusion
     rounds, iters = c["rounds"], c["iters"]
     solver.set_data(w, b)
     launch_shape = solver.launch_shape() if args.no_autotune else solver.autotune(3)
-    print(f"# launch shape (nt_y, nt_z, zc) = {launch_shape}", file=sys.stderr, flush=True)
+    if args.no_fusion:
+        solver.set_fusion(False)
+    fused = solver.fusion
+    print(f"# launch shape (nt_y, nt_z, zc) = {launch_shape}, fused x transforms: {fused}", file=sys.stderr,
+          flush=True)
 
     result = {}
 

@@ -772,34 +772,47 @@ spg_status spg_autotune(spg_problem* P, int32_t iters) {
   if (iters < 1 || iters > 1000) return set_err(P, SPG_E_INVAL, "iters must be in [1, 1000]");
   if (!P->data_set) return set_err(P, SPG_E_STATE, "spg_set_data has not succeeded");
   if (P->prof_on) return set_err(P, SPG_E_STATE, "profiling is active");
-  // coordinate search: for each knob, time its kernel class over `iters` iterations from
-  // the zero map for every candidate and keep the fastest
+  // coordinate search: for each knob, time the kernel classes it changes over `iters`
+  // iterations from the zero map for every candidate and keep the fastest.  The fusion
+  // knob (where the grid supports it) compares the fused stencil/prox kernel with the
+  // stencil kernel plus the separate x-axis sweeps.
   struct Knob {
     int* val;
-    int cls;
+    std::vector<int> cls;
     std::vector<int> cand;
   };
-  std::vector<Knob> knobs = {{&P->nt_y, SPG_KERNEL_FFT_Y_FWD, {16, 8}},
-                             {&P->nt_z, SPG_KERNEL_FFT_Z_WEIGHT, {16, 8}},
-                             {&P->zc, SPG_KERNEL_PROX_TV, {32, 16, 64}}};
+  int fused = P->fused ? 1 : 0;
+  std::vector<Knob> knobs = {{&P->nt_y, {SPG_KERNEL_FFT_Y_FWD}, {16, 8}},
+                             {&P->nt_z, {SPG_KERNEL_FFT_Z_WEIGHT}, {16, 8}}};
+  if (prox_fft_supported(P->d))
+    knobs.push_back({&fused, {SPG_KERNEL_PROX_TV, SPG_KERNEL_C2R_X, SPG_KERNEL_R2C_X}, {1, 0}});
+  knobs.push_back({&P->zc, {SPG_KERNEL_PROX_TV}, {32, 16, 64}});
   for (Knob& kb : knobs) {
     int best = *kb.val;
     double best_ms = 1e300;
     for (int c : kb.cand) {
       *kb.val = c;
+      P->fused = fused != 0;
       if ((s = spg_set_map(P, nullptr))) return s;
       if ((s = spg_run(P, 1, nullptr))) return s;  // warm
-      if ((s = spg_profile_begin(P, kb.cls, iters))) return s;
+      if ((s = spg_profile_begin(P, SPG_KERNEL_ALL, iters))) return s;
       if ((s = spg_run(P, iters, nullptr))) return s;
       double ms[SPG_KERNEL_COUNT];
       int32_t n[SPG_KERNEL_COUNT];
       if ((s = spg_profile_end(P, ms, n))) return s;
-      if (n[kb.cls] > 0 && ms[kb.cls] < best_ms) {
-        best_ms = ms[kb.cls];
+      double t = 0.0;
+      int launched = 0;
+      for (int k : kb.cls) {
+        t += ms[k];
+        launched += n[k];
+      }
+      if (launched > 0 && t < best_ms) {
+        best_ms = t;
         best = c;
       }
     }
     *kb.val = best;
+    P->fused = fused != 0;
   }
   return spg_set_map(P, nullptr);
 }

@@ -476,6 +476,7 @@ def test_autotune_picks_candidates_and_resets():
     assert float(g.get_map().abs().max()) == 0.0
     g.run(10)
     h = gpu_solver(shape, w, b, 0.02, 0.05, 1e-2)
+    h.set_fusion(g.fusion)  # the tuner may pick either x-transform path; shapes do not change results
     h.run(10)
     assert torch.equal(g.get_map(), h.get_map())
 
