@@ -286,9 +286,27 @@ struct RegPlan {
   }
 };
 
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v / 2); }
+
+// LDS placement of element e written by a stage of span Ns and radix R (and read by the
+// next stage) for one transform per row segment (ps = 1).  The stage writes land Ns*R
+// apart for lanes in different butterfly groups, which would pile onto a few of the 32
+// banks; XOR-ing the lane's bits [log2 Ns, log2 Ns*R) with address bits above them (so
+// the map is a bijection on [0, L)) spreads 32 consecutive lanes over all banks, and the
+// next stage's contiguous reads only permute within aligned blocks.  Power-of-two L only.
+template <int L, int Ns, int R>
+__device__ __forceinline__ int swz(int e) {
+  if constexpr ((L & (L - 1)) != 0 || Ns >= 32) {
+    return e;
+  } else {
+    constexpr int ks = Ns * R > 32 ? ilog2c(Ns * R) : 5;
+    return e ^ (((e >> ks) & (R - 1)) * Ns);
+  }
+}
+
 // act = false: the thread takes part in the barriers only (blocks whose threads do not all
-// hold a transform).
-template <int L, int TT, int S, bool INV>
+// hold a transform).  SWZ: LDS placement by swz (row transforms, ps = 1).
+template <int L, int TT, int S, bool INV, bool SWZ = false>
 __device__ __forceinline__ void reg_stage(float2 (&a)[reg_e(L, TT)], float* __restrict__ re,
                                           float* __restrict__ im, int ps, int q, const float2* __restrict__ twl,
                                           bool act = true) {
@@ -309,7 +327,9 @@ __device__ __forceinline__ void reg_stage(float2 (&a)[reg_e(L, TT)], float* __re
         if constexpr (first) {
           v[b][r] = a[b + r * (STR / T)];
         } else {
-          const int idx = (q + T * b + r * STR) * ps;
+          int e = q + T * b + r * STR;
+          if constexpr (SWZ) e = swz<L, P::span(S - 1), P::radix(S - 1)>(e);
+          const int idx = e * ps;
           v[b][r] = make_float2(re[idx], im[idx]);
         }
       }
@@ -339,7 +359,9 @@ __device__ __forceinline__ void reg_stage(float2 (&a)[reg_e(L, TT)], float* __re
       const int base = (j - k) * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int idx = (base + r * Ns) * ps;
+        int e = base + r * Ns;
+        if constexpr (SWZ) e = swz<L, Ns, R>(e);
+        const int idx = e * ps;
         re[idx] = v[b][r].x;
         im[idx] = v[b][r].y;
       }
@@ -348,21 +370,21 @@ __device__ __forceinline__ void reg_stage(float2 (&a)[reg_e(L, TT)], float* __re
   if constexpr (!last) __syncthreads();
 }
 
-template <int L, int TT, int S, bool INV, int SEND = RegPlan<L, TT>::ns>
+template <int L, int TT, int S, bool INV, int SEND = RegPlan<L, TT>::ns, bool SWZ = false>
 __device__ __forceinline__ void reg_stages(float2 (&a)[reg_e(L, TT)], float* re, float* im, int ps, int q,
                                            const float2* twl, bool act = true) {
   if constexpr (S < SEND) {
-    reg_stage<L, TT, S, INV>(a, re, im, ps, q, twl, act);
-    reg_stages<L, TT, S + 1, INV, SEND>(a, re, im, ps, q, twl, act);
+    reg_stage<L, TT, S, INV, SWZ>(a, re, im, ps, q, twl, act);
+    reg_stages<L, TT, S + 1, INV, SEND, SWZ>(a, re, im, ps, q, twl, act);
   }
 }
 
 // Transform the registers a[] of every thread.  Precondition: no thread still reads the
 // LDS data planes (barrier after their last use) and the twiddle table is visible.
-template <int L, bool INV, int TT = FftPlan<L>::T>
+template <int L, bool INV, int TT = FftPlan<L>::T, bool SWZ = false>
 __device__ __forceinline__ void fft_reg(float2 (&a)[reg_e(L, TT)], float* re, float* im, int ps, int q,
                                         const float2* twl, bool act = true) {
-  reg_stages<L, TT, 0, INV>(a, re, im, ps, q, twl, act);
+  reg_stages<L, TT, 0, INV, RegPlan<L, TT>::ns, SWZ>(a, re, im, ps, q, twl, act);
 }
 
 // Threads per column of the column passes: more threads for the long axes keep the
@@ -672,14 +694,14 @@ __global__ void __launch_bounds__(256) k_dc_nyquist(float2* __restrict__ S, int 
 // W = exp(-2 pi i / nx), packed X[0] = (X_0, X_M).  Inverse: Z[k] = E + i O with
 // E = X[k] + conj X[M-k], O = (X[k] - conj X[M-k]) conj(W^k), z = IFFT_M(Z), which is
 // the unnormalised inverse of the Hermitian row spectrum.
-// Block: NR rows; thread (row c = tid / T, q = tid % T); LDS row pitch M + 1.
+// Block: NR rows; thread (row c = tid / T, q = tid % T); LDS row pitch M + 4.
 
 template <int M, bool BF>
 __global__ void __launch_bounds__(256) k_r2c_x(const void* __restrict__ rin, float2* __restrict__ S, int nrows,
                                                const float2* __restrict__ twm, const float2* __restrict__ twn,
                                                int NR) {
-  __shared__ float s_re[(M + 1) * 16];
-  __shared__ float s_im[(M + 1) * 16];
+  __shared__ float s_re[(M + 4) * 16];  // row pitch = 4 (mod 8): two rows per 32 lanes
+  __shared__ float s_im[(M + 4) * 16];
   __shared__ float2 s_tw[M];
   constexpr int T = RegPlan<M>::T;
   constexpr int E = RegPlan<M>::E;
@@ -702,9 +724,9 @@ __global__ void __launch_bounds__(256) k_r2c_x(const void* __restrict__ rin, flo
   }
   for (int i = tid; i < M; i += blockDim.x) s_tw[i] = twm[i];
   __syncthreads();
-  float* re = s_re + c * (M + 1);
-  float* im = s_im + c * (M + 1);
-  fft_reg<M, false>(a, re, im, 1, q, s_tw);
+  float* re = s_re + c * (M + 4);
+  float* im = s_im + c * (M + 4);
+  fft_reg<M, false, RegPlan<M>::T, true>(a, re, im, 1, q, s_tw);
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < E; ++i) {
@@ -737,8 +759,8 @@ template <int M, bool BF>
 __global__ void __launch_bounds__(256) k_c2r_x(const float2* __restrict__ S, void* __restrict__ rout, int nrows,
                                                const float2* __restrict__ twm, const float2* __restrict__ twn,
                                                int NR) {
-  __shared__ float s_re[(M + 1) * 16];
-  __shared__ float s_im[(M + 1) * 16];
+  __shared__ float s_re[(M + 4) * 16];  // row pitch = 4 (mod 8): two rows per 32 lanes
+  __shared__ float s_im[(M + 4) * 16];
   __shared__ float2 s_tw[M];
   constexpr int T = RegPlan<M>::T;
   constexpr int E = RegPlan<M>::E;
@@ -756,8 +778,8 @@ __global__ void __launch_bounds__(256) k_c2r_x(const float2* __restrict__ S, voi
     wk[i] = twn[k];
   }
   for (int i = tid; i < M; i += blockDim.x) s_tw[i] = twm[i];
-  float* re = s_re + c * (M + 1);
-  float* im = s_im + c * (M + 1);
+  float* re = s_re + c * (M + 4);
+  float* im = s_im + c * (M + 4);
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     re[q + T * i] = a[i].x;
@@ -779,7 +801,7 @@ __global__ void __launch_bounds__(256) k_c2r_x(const float2* __restrict__ S, voi
     }
   }
   __syncthreads();
-  fft_reg<M, true>(a, re, im, 1, q, s_tw);
+  fft_reg<M, true, RegPlan<M>::T, true>(a, re, im, 1, q, s_tw);
   if (valid) {
     if constexpr (BF) {
       uint32_t* dst = reinterpret_cast<uint32_t*>(rout) + (long long)row * M;
@@ -1294,7 +1316,7 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
       }
     }
     __syncthreads();
-    fft_reg<M, false, FT>(v, fre, fim, 1, fq, s_tw, act);
+    fft_reg<M, false, FT, true>(v, fre, fim, 1, fq, s_tw, act);
     if (act && !fwd) {  // z = conj(FFT(conj Z)): interleaved real samples of the row
 #pragma unroll
       for (int i = 0; i < FE; ++i)
