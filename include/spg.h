@@ -162,9 +162,10 @@ spg_status spg_set_state(spg_problem* P, const void* d_buf, size_t bytes);
 /* Launch shapes: columns per tile of the y and z transform passes (8 or 16) and the z-slab
  * depth of the stencil kernel (4..512 planes).  spg_autotune times each knob in turn
  * (coordinate search over {16, 8}, {16, 8}, fused x transforms {on, off} where the grid
- * supports them (see spg_set_fusion), {32, 16, 64}) on `iters` iterations from the zero
- * map with HIP events and keeps the fastest; it leaves the map at 0 with the momentum
- * restarted.  Results are bitwise independent of the launch shape. */
+ * supports them (see spg_set_fusion), {32, 16, 64}) on `iters` iterations (after three
+ * untimed ones, so that the momentum term is active) from the zero map, with the penalty
+ * weights as set, with HIP events, and keeps the fastest; it leaves the map at 0 with the
+ * momentum restarted.  Results are bitwise independent of the launch shape. */
 spg_status spg_set_launch_shape(spg_problem* P, int32_t nt_y, int32_t nt_z, int32_t zc);
 spg_status spg_get_launch_shape(const spg_problem* P, int32_t* nt_y, int32_t* nt_z, int32_t* zc);
 spg_status spg_autotune(spg_problem* P, int32_t iters);
@@ -189,8 +190,11 @@ spg_status spg_get_fusion(const spg_problem* P, int32_t* enabled);
  * creates its own launch stream and one capture stream per problem (default priority).  spg_batch_run(K) synchronises each
  * problem's own stream, captures K iterations of every problem as parallel branches of one
  * graph (kernel nodes only), launches it, and makes each problem's stream wait for it: the
- * results equal K calls of spg_run per problem, bitwise.  spg_batch_destroy releases the
- * streams, events and graph, not the problems. */
+ * results equal K calls of spg_run per problem, bitwise.  When every problem is in the
+ * host-side iteration state the current graph was captured from (for instance after
+ * spg_set_map restarted each of them) and K is unchanged, the instantiated graph is
+ * launched again without a new capture.  spg_batch_destroy releases the streams, events
+ * and graph, not the problems. */
 typedef struct spg_batch spg_batch;
 spg_status spg_batch_create(spg_problem* const* problems, int32_t n, void* hip_stream, spg_batch** out);
 spg_status spg_batch_run(spg_batch* B, int32_t K);

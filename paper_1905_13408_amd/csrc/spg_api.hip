@@ -144,6 +144,7 @@ struct spg_problem {
   // depth of the stencil kernel
   int nt_y = 16, nt_z = 16, zc = PT_ZC;
   bool fused = false;  // fused x-axis transforms in the stencil/prox kernel
+  bool shared_gpu = false;  // being captured into a batch graph with other problems
   // unrolled solve recorded by spg_run_checkpointed for spg_vjp
   bool vjp_valid = false;
   int32_t vjp_K = 0, vjp_C = 0;
@@ -251,7 +252,7 @@ spg_status gradient_pipeline(spg_problem* P, bool obj, int* nA, int* nB, void* g
   prof_begin(P, SPG_KERNEL_FFT_Z_WEIGHT);
   // the objective variant writes one partial per block: 16-column tiles keep <= 8192 blocks
   SPG_CK(P, launch_fft_cols(d, P->S(), 2, obj ? 3 : 2, twz, wsp, csp, obj ? P->part() + kPartA : nullptr, st, nA,
-                            obj ? 16 : P->nt_z));
+                            obj ? 16 : P->nt_z, !P->shared_gpu));
   prof_end(P, SPG_KERNEL_FFT_Z_WEIGHT);
   prof_begin(P, SPG_KERNEL_DC_NYQUIST);
   SPG_CK(P, launch_dc_nyquist(d, P->S(), twz, P->at<float>(P->lay.w0p), P->at<float>(P->lay.wnyq),
@@ -794,7 +795,8 @@ spg_status spg_autotune(spg_problem* P, int32_t iters) {
       *kb.val = c;
       P->fused = fused != 0;
       if ((s = spg_set_map(P, nullptr))) return s;
-      if ((s = spg_run(P, 1, nullptr))) return s;  // warm
+      // warm, and past the first two iterations of a round (zero momentum: x_{k-1} unread)
+      if ((s = spg_run(P, 3, nullptr))) return s;
       if ((s = spg_profile_begin(P, SPG_KERNEL_ALL, iters))) return s;
       if ((s = spg_run(P, iters, nullptr))) return s;
       double ms[SPG_KERNEL_COUNT];
@@ -821,8 +823,51 @@ spg_status spg_autotune(spg_problem* P, int32_t iters) {
 
 // ---------------------------------------------------------------- batches in one HIP graph
 
+// Host state of a problem that the kernels of its next iterations depend on (launch
+// arguments: buffers, momenta, step, shapes, paths), and the part of it that advances.
+struct IterSig {
+  spg_params prm;
+  int store, cur, old, nt_y, nt_z, zc;
+  bool prior_set, primed, unif_u, unif_v, fused;
+  double lr, t, m_cur;
+  int32_t j;
+  static IterSig of(const spg_problem* P) {
+    IterSig g;
+    g.prm = P->prm;
+    g.store = P->store;
+    g.cur = P->cur;
+    g.old = P->old;
+    g.nt_y = P->nt_y;
+    g.nt_z = P->nt_z;
+    g.zc = P->zc;
+    g.prior_set = P->prior_set;
+    g.primed = P->primed;
+    g.unif_u = P->unif_u;
+    g.unif_v = P->unif_v;
+    g.fused = P->fused;
+    g.lr = P->lr;
+    g.t = P->t;
+    g.m_cur = P->m_cur;
+    g.j = P->j;
+    return g;
+  }
+  bool operator==(const IterSig& o) const {
+    const spg_params& a = prm;
+    const spg_params& b = o.prm;
+    return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.lambda == b.lambda && a.mu == b.mu && a.eps == b.eps &&
+           a.gamma == b.gamma && a.accel == b.accel && a.flags == b.flags && store == o.store && cur == o.cur &&
+           old == o.old && nt_y == o.nt_y && nt_z == o.nt_z && zc == o.zc && prior_set == o.prior_set &&
+           primed == o.primed && unif_u == o.unif_u && unif_v == o.unif_v && fused == o.fused && lr == o.lr &&
+           t == o.t && m_cur == o.m_cur && j == o.j;
+  }
+};
+
 struct spg_batch {
   std::vector<spg_problem*> probs;
+  // the instantiated graph is launched again without a new capture when every member is
+  // in the state it was captured from (same K): then the members advance to `post`
+  int32_t K_graph = 0;
+  std::vector<IterSig> pre, post;
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> join;
   hipEvent_t fork = nullptr, done = nullptr;
@@ -843,6 +888,61 @@ void batch_release_graph(spg_batch* B) {
     (void)hipGraphDestroy(B->graph);
     B->graph = nullptr;
   }
+}
+
+// Capture K iterations of every member as parallel branches of one graph (each member on
+// its own capture stream, forked from and joined into the origin stream), instantiate it,
+// launch it, and record the members' states before and after for later replays.
+spg_status batch_capture_and_launch(spg_batch* B, int32_t K) {
+  const int n = (int)B->probs.size();
+  batch_release_graph(B);
+  B->pre.resize(n);
+  B->post.resize(n);
+  for (int i = 0; i < n; ++i) B->pre[i] = IterSig::of(B->probs[i]);
+  std::vector<hipStream_t> saved(n);
+  auto fail = [&](hipError_t e, const char* what) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(B->origin, &g);
+    if (g) (void)hipGraphDestroy(g);
+    for (int i = 0; i < n; ++i)
+      if (saved[i]) B->probs[i]->stream = saved[i];
+    for (spg_problem* P : B->probs) {
+      P->shared_gpu = false;
+      P->sticky = true;  // host state advanced past the device
+    }
+    return fail_device(B->probs[0], e, what);
+  };
+  hipError_t e = hipStreamBeginCapture(B->origin, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return fail_device(B->probs[0], e, "hipStreamBeginCapture");
+  if ((e = hipEventRecord(B->fork, B->origin)) != hipSuccess) return fail(e, "hipEventRecord");
+  for (int i = 0; i < n; ++i) {
+    spg_problem* P = B->probs[i];
+    if ((e = hipStreamWaitEvent(B->streams[i], B->fork, 0)) != hipSuccess) return fail(e, "hipStreamWaitEvent");
+    saved[i] = P->stream;
+    P->stream = B->streams[i];
+    P->vjp_valid = false;
+    // the members' kernels run side by side: no persistent grids that each fill the GPU
+    P->shared_gpu = true;
+    for (int it = 0; it < K; ++it)
+      if (iterate_once(P, nullptr) != SPG_OK) return fail(hipErrorUnknown, P->err);
+    P->shared_gpu = false;
+    if ((e = hipEventRecord(B->join[i], B->streams[i])) != hipSuccess) return fail(e, "hipEventRecord");
+    if ((e = hipStreamWaitEvent(B->origin, B->join[i], 0)) != hipSuccess) return fail(e, "hipStreamWaitEvent");
+  }
+  e = hipStreamEndCapture(B->origin, &B->graph);
+  for (int i = 0; i < n; ++i) B->probs[i]->stream = saved[i];
+  if (e != hipSuccess) {
+    for (spg_problem* P : B->probs) P->sticky = true;
+    return fail_device(B->probs[0], e, "hipStreamEndCapture");
+  }
+  if ((e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0)) != hipSuccess ||
+      (e = hipGraphLaunch(B->exec, B->origin)) != hipSuccess || (e = hipEventRecord(B->done, B->origin)) != hipSuccess) {
+    for (spg_problem* P : B->probs) P->sticky = true;
+    return fail_device(B->probs[0], e, "graph launch");
+  }
+  for (int i = 0; i < n; ++i) B->post[i] = IterSig::of(B->probs[i]);
+  B->K_graph = K;
+  return SPG_OK;
 }
 }  // namespace
 
@@ -899,47 +999,35 @@ spg_status spg_batch_run(spg_batch* B, int32_t K) {
     if (P->prof_on) return set_err(P, SPG_E_STATE, "profiling is active");
   }
   if (K == 0) return SPG_OK;
-  batch_release_graph(B);
   const int n = (int)B->probs.size();
   // inputs set on the problems' own streams and the caller's stream must be complete
   // before the graph starts
   for (spg_problem* P : B->probs)
     if (hipStreamSynchronize(P->stream) != hipSuccess) return fail_device(P, hipErrorUnknown, "stream sync");
   if (hipStreamSynchronize(B->user) != hipSuccess) return fail_device(B->probs[0], hipErrorUnknown, "stream sync");
-  std::vector<hipStream_t> saved(n);
-  auto fail = [&](hipError_t e, const char* what) {
-    hipGraph_t g = nullptr;
-    (void)hipStreamEndCapture(B->origin, &g);
-    if (g) (void)hipGraphDestroy(g);
-    for (int i = 0; i < n; ++i)
-      if (saved[i]) B->probs[i]->stream = saved[i];
-    for (spg_problem* P : B->probs) P->sticky = true;  // host state advanced past the device
-    return fail_device(B->probs[0], e, what);
-  };
-  hipError_t e = hipStreamBeginCapture(B->origin, hipStreamCaptureModeRelaxed);
-  if (e != hipSuccess) return fail_device(B->probs[0], e, "hipStreamBeginCapture");
-  if ((e = hipEventRecord(B->fork, B->origin)) != hipSuccess) return fail(e, "hipEventRecord");
-  for (int i = 0; i < n; ++i) {
-    spg_problem* P = B->probs[i];
-    if ((e = hipStreamWaitEvent(B->streams[i], B->fork, 0)) != hipSuccess) return fail(e, "hipStreamWaitEvent");
-    saved[i] = P->stream;
-    P->stream = B->streams[i];
-    P->vjp_valid = false;
-    for (int it = 0; it < K; ++it)
-      if (iterate_once(P, nullptr) != SPG_OK) return fail(hipErrorUnknown, P->err);
-    if ((e = hipEventRecord(B->join[i], B->streams[i])) != hipSuccess) return fail(e, "hipEventRecord");
-    if ((e = hipStreamWaitEvent(B->origin, B->join[i], 0)) != hipSuccess) return fail(e, "hipStreamWaitEvent");
-  }
-  e = hipStreamEndCapture(B->origin, &B->graph);
-  for (int i = 0; i < n; ++i) B->probs[i]->stream = saved[i];
-  if (e != hipSuccess) {
-    for (spg_problem* P : B->probs) P->sticky = true;
-    return fail_device(B->probs[0], e, "hipStreamEndCapture");
-  }
-  if ((e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0)) != hipSuccess ||
-      (e = hipGraphLaunch(B->exec, B->origin)) != hipSuccess || (e = hipEventRecord(B->done, B->origin)) != hipSuccess) {
-    for (spg_problem* P : B->probs) P->sticky = true;
-    return fail_device(B->probs[0], e, "graph launch");
+  bool replay = B->exec && K == B->K_graph && (int)B->pre.size() == n;
+  for (int i = 0; replay && i < n; ++i) replay = IterSig::of(B->probs[i]) == B->pre[i];
+  hipError_t e;
+  if (replay) {
+    if ((e = hipGraphLaunch(B->exec, B->origin)) != hipSuccess || (e = hipEventRecord(B->done, B->origin)) != hipSuccess) {
+      for (spg_problem* P : B->probs) P->sticky = true;
+      return fail_device(B->probs[0], e, "graph launch");
+    }
+    for (int i = 0; i < n; ++i) {
+      spg_problem* P = B->probs[i];
+      const IterSig& g = B->post[i];
+      P->primed = g.primed;
+      P->cur = g.cur;
+      P->old = g.old;
+      P->t = g.t;
+      P->m_cur = g.m_cur;
+      P->j = g.j;
+      P->iters_done += K;
+      P->vjp_valid = false;
+    }
+  } else {
+    spg_status s = batch_capture_and_launch(B, K);
+    if (s) return s;
   }
   // later work on each problem's own stream and on the caller's stream starts after the graph
   for (spg_problem* P : B->probs)

@@ -64,9 +64,12 @@ bool prox_fft_supported(const Dims& d);
 hipError_t launch_prox_fft(const Dims& d, const ProxArgs& a, float2* S, const float2* tw_m, const float2* tw_n,
                            int store, hipStream_t st);
 
+// persist: the fused z modes run persistent blocks (false: one block per tile, for
+// problems that share the GPU with concurrent work)
 hipError_t launch_fft_cols(const Dims& d, float2* S, int axis /*1 = y, 2 = z*/, int mode,
                            const float2* tw, const float* ws, const float2* cs, double* partials,
-                           hipStream_t st, int* nblocks_out, int nt = 16 /* columns per tile: 8 or 16 */);
+                           hipStream_t st, int* nblocks_out, int nt = 16 /* columns per tile: 8 or 16 */,
+                           bool persist = true);
 hipError_t launch_dc_nyquist(const Dims& d, float2* S, const float2* tw_z, const float* w0p,
                              const float* wnyq, const float2* c0p, const float2* cnyq, double* partials,
                              hipStream_t st, int* nblocks_out);

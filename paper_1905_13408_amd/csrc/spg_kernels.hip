@@ -1965,17 +1965,18 @@ static int cu_count() {
 }
 
 // Fused z passes: one persistent block per resident slot (CUs x blocks per CU), rounded
-// down to a multiple of the 8 XCDs, or one block per tile when there are fewer tiles.
+// down to a multiple of the 8 XCDs, or one block per tile when there are fewer tiles or
+// when persist is false (problems sharing the GPU with others).
 template <int L, int MODE>
 static hipError_t launch_zw(float2* S, int P, int ntiles, int total, long long pstride, long long bstride,
                             const float2* tw, const float* ws, const float2* cs, double* partials, int NT, int T,
-                            hipStream_t st, int* nblocks_out) {
+                            bool persist, hipStream_t st, int* nblocks_out) {
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fft_zw<L, MODE>, NT * T, 0) != hipSuccess || occ < 1)
     occ = 1;
   long long g = (long long)cu_count() * occ;
   if (g > 4096) g = 4096;  // the objective partials of mode 3 hold one value per block
-  if (g >= total) g = total;
+  if (g >= total || (!persist && MODE != 3)) g = total;
   else if (g >= 8) g &= ~7LL;
   if (nblocks_out) *nblocks_out = (int)g;
   k_fft_zw<L, MODE><<<dim3((unsigned)g), dim3(NT * T), 0, st>>>(S, P, ntiles, total, pstride, bstride, tw, ws, cs,
@@ -1984,7 +1985,8 @@ static hipError_t launch_zw(float2* S, int P, int ntiles, int total, long long p
 }
 
 hipError_t launch_fft_cols(const Dims& d, float2* S, int axis, int mode, const float2* tw, const float* ws,
-                           const float2* cs, double* partials, hipStream_t st, int* nblocks_out, int nt) {
+                           const float2* cs, double* partials, hipStream_t st, int* nblocks_out, int nt,
+                           bool persist) {
   const int L = axis == 1 ? d.ny : d.nz;
   if (nt != 8 && nt != 16) return hipErrorInvalidValue;
   if (mode < 0 || mode > 4 || (mode >= 2 && axis != 2)) return hipErrorInvalidValue;
@@ -2007,7 +2009,8 @@ hipError_t launch_fft_cols(const Dims& d, float2* S, int axis, int mode, const f
     return hipGetLastError();
   }
 #define SPG_ZW(MODE_) \
-  return launch_zw<L_, MODE_>(S, d.P, ntiles, total, pstride, bstride, tw, ws, cs, partials, NT, T, st, nblocks_out)
+  return launch_zw<L_, MODE_>(S, d.P, ntiles, total, pstride, bstride, tw, ws, cs, partials, NT, T, persist, st, \
+                              nblocks_out)
   switch (mode) {
     case 2: SPG_DISPATCH_L(L, SPG_ZW(2)); break;
     case 3: SPG_DISPATCH_L(L, SPG_ZW(3)); break;

@@ -521,6 +521,33 @@ def test_batch_graph_matches_eager_runs_bitwise():
     batch.close()
 
 
+def test_batch_graph_replay_matches_eager_runs():
+    announce("batch graph replay (same start state) vs eager")
+    members = _batch_members(63)
+    solvers, refs = [], []
+    for shape, vol, lam, mu in members:
+        for lst in (solvers, refs):
+            s = spg.SPGSolver(shape, lam, mu, 1e-3)
+            s.set_data(vol.w, vol.b)
+            lst.append(s)
+    batch = spg.SPGBatch(solvers)
+    for K in (6, 6, 6, 4):   # the second and third launches replay the instantiated graph
+        for s in solvers + refs:
+            s.set_map(None)
+        batch.run(K)
+        for r in refs:
+            r.run(K)
+        for s, r in zip(solvers, refs):
+            assert torch.equal(s.get_map(), r.get_map())
+    # a replay continues where the graph left every member: the next run starts elsewhere
+    batch.run(4)
+    for r in refs:
+        r.run(4)
+    for s, r in zip(solvers, refs):
+        assert torch.equal(s.get_map(), r.get_map())
+    batch.close()
+
+
 def test_batch_member_160_vs_oracle():
     shape = (160, 160, 160)
     announce("batch member 160^3 vs oracle")
