@@ -505,22 +505,18 @@ __global__ void __launch_bounds__(16 * ColT<L>::T) k_fft_zw(float2* __restrict__
   const int tid = threadIdx.x;
   const int c = tid % NT, q = tid / NT;
   static_assert(MODE >= 2 && MODE <= 4, "fused z modes");
-  // Persistent blocks that load the next tile while transforming the current one.  Work
-  // units are PR = 2 neighbouring kx tiles (the two halves of the 128-byte lines of the
-  // folded weight), taken back to back by one block so that each weight line is fetched
-  // once, in ky-fastest order: unit u is (ky = u % ny, kx tiles PR (u / ny) + h), and
-  // block b takes units b, b + G, ...
+  // Persistent blocks that load the next tile while transforming the current one: with a
+  // grid of 8k blocks, XCD x (= blockIdx % 8) owns the contiguous tile range
+  // [x chunk, (x+1) chunk) and its k-th block walks that range with stride k, so tiles
+  // that share 128-byte lines (the folded weight rows of neighbouring 16-column tiles)
+  // are in flight in one L2 at the same time.
   const int G = gridDim.x;
-  const int nbat = total / ntiles;  // ky rows
-  const int PR = (ntiles % 2 == 0) ? 2 : 1;
-  const int nunits = total / PR;
-  auto tile_of = [&](int sq) -> int {  // the sq-th tile of this block, or -1 past the end
-    const int u = (int)blockIdx.x + (sq / PR) * G;
-    if (u >= nunits) return -1;
-    return (u % nbat) * ntiles + (u / nbat) * PR + (sq % PR);
-  };
-  int sq = 0;
-  int t = tile_of(0);
+  const bool split = G >= 8 && (G & 7) == 0;
+  const int xcd = split ? (int)(blockIdx.x & 7u) : 0;
+  const int chunk = split ? (total + 7) >> 3 : total;
+  const int nb = split ? G >> 3 : G;
+  int t = xcd * chunk + (split ? (int)(blockIdx.x >> 3) : (int)blockIdx.x);
+  const int t_end = min(total, xcd * chunk + chunk);
   // Block-uniform tile base pointers and unsigned 32-bit per-lane byte offsets of the
   // complex elements (every offset in a column is below nz*ny*P*8 <= 2^29 bytes), so the
   // loads take a scalar base and a 32-bit vector offset; the fp32 weight uses half the
@@ -536,7 +532,7 @@ __global__ void __launch_bounds__(16 * ColT<L>::T) k_fft_zw(float2* __restrict__
   };
 
   float2 a[E];
-  if (t >= 0) {
+  if (t < t_end) {
     const float2* __restrict__ Sb = S + tile_base(t);
     const unsigned o = lane_off(t);
 #pragma unroll
@@ -544,7 +540,7 @@ __global__ void __launch_bounds__(16 * ColT<L>::T) k_fft_zw(float2* __restrict__
   }
   for (int i = tid; i < L; i += blockDim.x) s_tw[i] = tw[i];
   double acc = 0.0;
-  while (t >= 0) {
+  for (; t < t_end; t += nb) {
     __syncthreads();  // twiddles visible; the previous tile's last stage read the LDS planes
     // The lane indices pass through an empty asm statement so that the per-stage LDS
     // addresses derived from them are formed inside the loop where they are used, not
@@ -557,8 +553,8 @@ __global__ void __launch_bounds__(16 * ColT<L>::T) k_fft_zw(float2* __restrict__
     const int kx = (t % ntiles) * NT + cl;
     const bool valid = kx < P;
     const unsigned o = lane_off(t);
-    const int tn = tile_of(sq + 1);
-    const bool more = tn >= 0;  // block-uniform
+    const int tn = t + nb;
+    const bool more = tn < t_end;  // block-uniform
     float2 nxt[E];
     float wv[E];
     float2 cv[E];
@@ -606,8 +602,6 @@ __global__ void __launch_bounds__(16 * ColT<L>::T) k_fft_zw(float2* __restrict__
 #pragma unroll
       for (int i = 0; i < E; ++i) a[i] = nxt[i];
     }
-    ++sq;
-    t = tn;
   }
   if constexpr (MODE == 3) {
     const double r = block_reduce<RED_OP_SUM>(acc, s_red);
@@ -1970,9 +1964,9 @@ static int cu_count() {
   return n;
 }
 
-// Fused z passes: one persistent block per resident slot (CUs x blocks per CU), or one
-// block per work unit when there are fewer units or when persist is false (problems
-// sharing the GPU with others).
+// Fused z passes: one persistent block per resident slot (CUs x blocks per CU), rounded
+// down to a multiple of the 8 XCDs, or one block per tile when there are fewer tiles or
+// when persist is false (problems sharing the GPU with others).
 template <int L, int MODE>
 static hipError_t launch_zw(float2* S, int P, int ntiles, int total, long long pstride, long long bstride,
                             const float2* tw, const float* ws, const float2* cs, double* partials, int NT, int T,
@@ -1980,10 +1974,10 @@ static hipError_t launch_zw(float2* S, int P, int ntiles, int total, long long p
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fft_zw<L, MODE>, NT * T, 0) != hipSuccess || occ < 1)
     occ = 1;
-  const int nunits = (ntiles % 2 == 0) ? total / 2 : total;  // work units of the kernel
   long long g = (long long)cu_count() * occ;
   if (g > 4096) g = 4096;  // the objective partials of mode 3 hold one value per block
-  if (g >= nunits || (!persist && MODE != 3)) g = nunits;
+  if (g >= total || (!persist && MODE != 3)) g = total;
+  else if (g >= 8) g &= ~7LL;
   if (nblocks_out) *nblocks_out = (int)g;
   k_fft_zw<L, MODE><<<dim3((unsigned)g), dim3(NT * T), 0, st>>>(S, P, ntiles, total, pstride, bstride, tw, ws, cs,
                                                                partials, NT);
