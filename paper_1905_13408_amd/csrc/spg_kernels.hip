@@ -1206,11 +1206,14 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
     if constexpr (BF) return bf16_to_f32(ld_at(b, o * 2u));
     else return ld_at(b, o * 4u);
   };
-  auto fetch_plane = [&](int zz, RawX* own, RawX& halo, float* vv) {
+  auto fetch_x = [&](int zz, RawX* own, RawX& halo) {
     const long long pz = pz_of(zz);
 #pragma unroll
     for (int h = 0; h < NO; ++h) fetch_one(pz, own_off[h], own[h]);
     fetch_one(pz, halo_off, halo);
+  };
+  auto fetch_v = [&](int zz, float* vv) {
+    const long long pz = pz_of(zz);
     if (a.v) {
 #pragma unroll
       for (int h = 0; h < NO; ++h) vv[h] = ld_w(a.v, pz, own_off[h]);
@@ -1367,14 +1370,16 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
   fetch_spec(z0, sa);
   {
     double d1[NO], d2[NO];
-    fetch_plane(z0 - 1, rown, rhalo, rv);
+    fetch_x(z0 - 1, rown, rhalo);
     store_plane(z0 - 1, rown, rhalo, d1, d2);
-    fetch_plane(z0, rown, rhalo, rv);
+    fetch_x(z0, rown, rhalo);
+    fetch_v(z0, rv);
     store_plane(z0, rown, rhalo, own_y, own_xk);
   }
   transform_phase(z0, z0, z0, sa);  // inverse half only; ends with a barrier
   compute_sc(z0, rv);
-  fetch_plane(z0 + 1, rown, rhalo, rv);
+  fetch_x(z0 + 1, rown, rhalo);
+  fetch_v(z0 + 1, rv);
   fetch_out(z0, u_cur, xq_cur);
   fetch_spec(z0 + KB, sa);
 
@@ -1388,11 +1393,13 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
 #pragma unroll
       for (int h = 0; h < NO; ++h) asm volatile("" : "+v"(own_off[h]));
       asm volatile("" : "+v"(fr), "+v"(fq));
-      // y of plane z+1 from the words fetched during the previous step
+      // y of plane z+1 from the words fetched during the previous step; the words of plane
+      // z+2 are requested at once, its v after sc(z+1) has used that of plane z+1
       store_plane(z + 1, rown, rhalo, nxt_y, nxt_xk);
+      if (z + 1 < z1) fetch_x(z + 2, rown, rhalo);
       __syncthreads();
       compute_sc(z + 1, rv);
-      if (z + 1 < z1) fetch_plane(z + 2, rown, rhalo, rv);  // in flight until the next step
+      if (z + 1 < z1) fetch_v(z + 2, rv);
       __syncthreads();
       // ---- outputs of plane z (as k_prox_tv)
       {
