@@ -1268,10 +1268,14 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
     const float inv = n2 > a.eps * a.eps ? rsqrtf(n2) : 1.0f / a.eps;
     return vv * inv;
   };
-  auto compute_sc = [&](int zz, const float* vv) {
+  // writes the ring slot of plane zz and returns the thread's own values in sco
+  auto compute_sc = [&](int zz, const float* vv, float* sco) {
     float(*SC)[NX] = sSC[zz & 1];
 #pragma unroll
-    for (int h = 0; h < NO; ++h) SC[r + 2 * h][x] = sc_at(zz, r + 2 * h, vv[h]);
+    for (int h = 0; h < NO; ++h) {
+      sco[h] = sc_at(zz, r + 2 * h, vv[h]);
+      SC[r + 2 * h][x] = sco[h];
+    }
     if (r == 1) SC[TY][x] = sc_at(zz, TY, vv[NO]);
   };
   // One transform phase.  Forward half (fr < NR): the y_{k+1} rows of the batch at plane
@@ -1377,7 +1381,10 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
     store_plane(z0, rown, rhalo, own_y, own_xk);
   }
   transform_phase(z0, z0, z0, sa);  // inverse half only; ends with a barrier
-  compute_sc(z0, rv);
+  {
+    float sc0[NO];
+    compute_sc(z0, rv, sc0);
+  }
   fetch_x(z0 + 1, rown, rhalo);
   fetch_v(z0 + 1, rv);
   fetch_out(z0, u_cur, xq_cur);
@@ -1398,16 +1405,17 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
       store_plane(z + 1, rown, rhalo, nxt_y, nxt_xk);
       if (z + 1 < z1) fetch_x(z + 2, rown, rhalo);
       __syncthreads();
-      compute_sc(z + 1, rv);
+      // sc(z+1) into its ring slot (read by the next step) and, for this thread's own
+      // voxels, straight into the outputs of plane z: one phase, no barrier between
+      float sc1[NO];
+      compute_sc(z + 1, rv, sc1);
       if (z + 1 < z1) fetch_v(z + 2, rv);
-      __syncthreads();
       // ---- outputs of plane z (as k_prox_tv)
       {
         const float(*Ym)[NX] = sY[slot3(z - 1)];
         const float(*Y0)[NX] = sY[slot3(z)];
         const float(*Y1)[NX] = sY[slot3(z + 1)];
         const float(*SC0)[NX] = sSC[z & 1];
-        const float(*SC1)[NX] = sSC[(z + 1) & 1];
         float(*G)[NX] = sG[z - zb];
         const long long pz = (long long)z * plane;
         float* __restrict__ xnh = a.xn_hi + pz;
@@ -1423,7 +1431,7 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
           const float pxc = __fmul_rn(sc, yc - Y0[ly + 1][xm]);
           const float pxn = __fmul_rn(SC0[ly][xp], Y0[ly + 1][xp] - yc);
           const float pyn = __fmul_rn(SC0[ly + 1][x], Y0[ly + 2][x] - yc);
-          const float pzn = __fmul_rn(SC1[ly][x], Y1[ly + 1][x] - yc);
+          const float pzn = __fmul_rn(sc1[h], Y1[ly + 1][x] - yc);
           const float gtv = pzc + pyc + pxc - pxn - pyn - pzn;
           const float gd = G[ly][x];
           const float uu = u_cur[h];
