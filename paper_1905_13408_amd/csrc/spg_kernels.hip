@@ -530,6 +530,16 @@ __global__ void __launch_bounds__(16 * ColT<L>::T) k_fft_zw(float2* __restrict__
   auto lane_off = [&](int tt) -> unsigned {
     return ((unsigned)((tt % ntiles) * NT + c < P ? c : 0) + (unsigned)q * ps) * 8u;
   };
+  // folded weight / data term: tile-major groups of WG = min(16, P) columns along z
+  const int WG = P < 16 ? P : 16;
+  auto wc_base = [&](int tt) -> long long {
+    const int kx0 = (tt % ntiles) * NT;
+    return ((long long)(tt / ntiles) * (P / WG) + kx0 / WG) * L * WG + kx0 % WG;
+  };
+  auto wc_off = [&](int tt) -> unsigned {  // element offset of the lane in its tile
+    return (unsigned)((tt % ntiles) * NT + c < P ? c : 0) + (unsigned)(q * WG);
+  };
+  const unsigned wstep = (unsigned)(T * WG);
 
   float2 a[E];
   if (t < t_end) {
@@ -560,13 +570,15 @@ __global__ void __launch_bounds__(16 * ColT<L>::T) k_fft_zw(float2* __restrict__
     float2 cv[E];
     reg_stages<L, T, 0, false, 1>(a, re, im, NT, ql, s_tw);
     // the folded weight and data term load during the remaining forward stages
-    const float* __restrict__ wsb = ws + ub;
+    const long long wb = wc_base(t);
+    const unsigned ow = wc_off(t);
+    const float* __restrict__ wsb = ws + wb;
 #pragma unroll
-    for (int i = 0; i < E; ++i) wv[i] = ld_at(wsb, (o + i * step) >> 1);
+    for (int i = 0; i < E; ++i) wv[i] = ld_at(wsb, (ow + i * wstep) * 4u);
     if constexpr (MODE != 4) {
-      const float2* __restrict__ csb = cs + ub;
+      const float2* __restrict__ csb = cs + wb;
 #pragma unroll
-      for (int i = 0; i < E; ++i) cv[i] = ld_at(csb, o + i * step);
+      for (int i = 0; i < E; ++i) cv[i] = ld_at(csb, (ow + i * wstep) * 8u);
     } else {
 #pragma unroll
       for (int i = 0; i < E; ++i) cv[i] = make_float2(0.f, 0.f);
@@ -1534,6 +1546,16 @@ __global__ void k_fill(float* __restrict__ dst, long long n, float value) {
 // Hermitian part of w (A x - b)):  w~ = (w_k + w_{-k})/2,  c = (w_k b_k + w_{-k} conj b_{-k})/2,
 // stored scaled for unnormalised transforms: ws = w~ / nvox, cs = c / sqrt(nvox).
 // Partial: max w~.
+// Layout of the folded weight and data term (read only by the fused z pass): groups of
+// WC_G = min(16, P) consecutive kx, each group contiguous along kz, i.e.
+// [ky][kx / WC_G][kz][kx % WC_G], so that a 16-column tile reads them as one contiguous
+// run along z instead of 64- and 128-byte pieces a plane apart.
+__host__ __device__ __forceinline__ int wc_group(int P) { return P < 16 ? P : 16; }
+__device__ __forceinline__ long long wc_index(const Dims& d, int kz, int ky, int kx) {
+  const int G = wc_group(d.P);
+  return (((long long)ky * (d.P / G) + kx / G) * d.nz + kz) * G + kx % G;
+}
+
 __global__ void __launch_bounds__(256) k_fold(Dims d, const float* __restrict__ w, const float2* __restrict__ b,
                                               float* __restrict__ ws, float* __restrict__ w0p,
                                               float* __restrict__ wnyq, float2* __restrict__ cs,
@@ -1563,7 +1585,7 @@ __global__ void __launch_bounds__(256) k_fold(Dims d, const float* __restrict__ 
     const float2 csv = make_float2((float)(cr * inv_sqrt_n), (float)(ci * inv_sqrt_n));
     const long long op = (long long)ky * d.nz + kz;  // [ky][kz] planes of kx = 0 and nx/2
     if (kx < P) {
-      const long long o = ((long long)kz * d.ny + ky) * P + kx;
+      const long long o = wc_index(d, kz, ky, kx);
       ws[o] = wsv;
       cs[o] = csv;
       if (kx == 0) {
