@@ -1140,7 +1140,9 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
 // one halo row on each side, and sc = v / max(eps, |Dy|) on two planes (z, z+1) with
 // the row below the tile; the p = sc Dy terms of D^T p are formed from these rings.
 // Thread (x = tid % NX, r = tid / NX) owns rows r + 2h (h < PF_TY/2) and halo row -1
-// (r = 0) or PF_TY (r = 1); the next plane's words are prefetched one step ahead.
+// (r = 0) or PF_TY (r = 1).  A z step has two phases: (1) y(z+1) into the ring, and the
+// iterate words of plane z+2 requested at once; (2) after a barrier, sc(z+1) into its slot
+// and, for the thread's own voxels, straight into the outputs of plane z; then a barrier.
 // The row transforms are batched over PF_KB planes: the gradient rows of a batch sit in
 // LDS while its planes are stepped (each plane's y_{k+1} rows replace its gradient rows),
 // then one transform phase on all threads takes the batch's y_{k+1} rows forward into S
