@@ -4,8 +4,8 @@
 ``bench.py`` (counter values in KiB per dispatch) plus the same two counters read on a
 plain device copy of known size into per-kernel HBM bytes per launch.  The copy gives
 the scale of each counter (bytes moved / counter bytes).  The record stores the
-SHA-256 of the kernel source it was taken on, so a benchmark can tell whether the
-figures still describe the kernels it runs.
+SHA-256 of the kernel source it was taken on (comments and blank space left out), so a
+benchmark can tell whether the figures still describe the kernels it runs.
 
     python -m paper_1905_13408_amd.profiling FETCH.csv WRITE.csv COPY_FETCH.csv COPY_WRITE.csv \
         COPY_BYTES OUT.txt "command text"
@@ -32,8 +32,16 @@ FUSED = "spg::k_prox_fft<"  # stencil/prox kernel with the x-axis transforms ins
 
 
 def source_sha256(path: str = KERNEL_SOURCE) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    """SHA-256 of the kernel source without its comments and blank space, so that a record
+    stays valid across edits that cannot change the kernels."""
+    import re
+
+    with open(path) as f:
+        txt = f.read()
+    txt = re.sub(r"/\*.*?\*/", " ", txt, flags=re.S)     # block comments
+    txt = re.sub(r"//[^\n]*", " ", txt)                    # line comments
+    txt = " ".join(txt.split())                            # whitespace runs
+    return hashlib.sha256(txt.encode()).hexdigest()
 
 
 def _per_kernel(path):
