@@ -162,7 +162,7 @@ spg_status spg_set_state(spg_problem* P, const void* d_buf, size_t bytes);
 /* Launch shapes: columns per tile of the y and z transform passes (8 or 16) and the z-slab
  * depth of the stencil kernel (4..512 planes).  spg_autotune times each knob in turn
  * (coordinate search over {16, 8}, {16, 8}, fused x transforms {on, off} where the grid
- * supports them (see spg_set_fusion), {32, 16, 64, 128}) on `iters` iterations (after three
+ * supports them (see spg_set_fusion), {32, 16, 64, 128, 256}) on `iters` iterations (after three
  * untimed ones, so that the momentum term is active) from the zero map, with the penalty
  * weights as set, with HIP events, and keeps the fastest; it leaves the map at 0 with the
  * momentum restarted.  Results are bitwise independent of the launch shape. */

@@ -787,7 +787,7 @@ spg_status spg_autotune(spg_problem* P, int32_t iters) {
                              {&P->nt_z, {SPG_KERNEL_FFT_Z_WEIGHT}, {16, 8}}};
   if (prox_fft_supported(P->d))
     knobs.push_back({&fused, {SPG_KERNEL_PROX_TV, SPG_KERNEL_C2R_X, SPG_KERNEL_R2C_X}, {1, 0}});
-  knobs.push_back({&P->zc, {SPG_KERNEL_PROX_TV}, {32, 16, 64, 128}});
+  knobs.push_back({&P->zc, {SPG_KERNEL_PROX_TV}, {32, 16, 64, 128, 256}});
   for (Knob& kb : knobs) {
     int best = *kb.val;
     double best_ms = 1e300;
