@@ -187,14 +187,19 @@ spg_status spg_get_fusion(const spg_problem* P, int32_t* enabled);
 /* Batches: independent problems of any sizes (gold-standard half-maps, class volumes)
  * advanced together in one HIP graph.  spg_batch_create takes n (1..64) distinct problems
  * and the caller's stream (hipStream_t, NULL = default), which waits for every graph; it
- * creates its own launch stream and one capture stream per problem (default priority).  spg_batch_run(K) synchronises each
- * problem's own stream, captures K iterations of every problem as parallel branches of one
- * graph (kernel nodes only), launches it, and makes each problem's stream wait for it: the
- * results equal K calls of spg_run per problem, bitwise.  When every problem is in the
+ * creates its own launch stream and one capture stream per problem (default priority).
+ * spg_batch_run(K) synchronises each problem's own stream, captures K iterations of every
+ * problem as parallel branches of one graph (kernel nodes only), launches it, and makes
+ * each problem's stream wait for it: the results equal K calls of spg_run per problem,
+ * bitwise.  When every problem is in the
  * host-side iteration state the current graph was captured from (for instance after
  * spg_set_map restarted each of them) and K is unchanged, the instantiated graph is
- * launched again without a new capture.  spg_batch_destroy releases the streams, events
- * and graph, not the problems. */
+ * launched again without a new capture.  Inside the graph the fused z pass runs one block
+ * per work unit instead of persistent blocks, so that the branches share the GPU.  The
+ * problems must outlive the batch and must not be used from another thread during
+ * spg_batch_run; a problem whose run fails is left in SPG_E_DEVICE state like any other
+ * device error.  spg_batch_destroy releases the streams, events and graph, not the
+ * problems. */
 typedef struct spg_batch spg_batch;
 spg_status spg_batch_create(spg_problem* const* problems, int32_t n, void* hip_stream, spg_batch** out);
 spg_status spg_batch_run(spg_batch* B, int32_t K);
