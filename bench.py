@@ -248,6 +248,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel HIP events")
     ap.add_argument("--copy-calib", action="store_true", help="only run the copy kernel used to scale HBM counters")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--launch-shape", type=int, nargs=3, metavar=("NT_Y", "NT_Z", "ZC"), default=None,
+                    help="fix the launch shape instead of autotuning it")
     ap.add_argument("--no-fusion", action="store_true", help="run the x-axis transforms as separate sweeps")
     args = ap.parse_args()
 
@@ -292,7 +294,11 @@ def main():
     # values do not change the timing); every step below starts from uniform weights again
     ones = torch.ones(shape, dtype=torch.float32, device="cuda")
     solver.set_penalty_weights(ones, ones)
-    launch_shape = solver.launch_shape() if args.no_autotune else solver.autotune(3)
+    if args.launch_shape:
+        solver.set_launch_shape(*args.launch_shape)
+        launch_shape = solver.launch_shape()
+    else:
+        launch_shape = solver.launch_shape() if args.no_autotune else solver.autotune(3)
     del ones
     if args.no_fusion:
         solver.set_fusion(False)

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -302,6 +303,7 @@ ProxArgs prox_args(spg_problem* P, int nxt, double m, double m_next) {
   a.lam = P->prm.lambda;
   a.mu = P->prm.mu;
   a.eps = (float)P->prm.eps;
+  a.eps2_normal = a.eps * a.eps >= FLT_MIN ? 1 : 0;
   a.zc = P->zc;
   return a;
 }

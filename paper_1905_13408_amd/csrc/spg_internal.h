@@ -51,6 +51,7 @@ struct ProxArgs {
   double m, m_next;             // momentum for y_k and for y_{k+1}
   double lr, lam, mu, gamma;
   float eps;
+  int eps2_normal;              // eps * eps (fp32) is a normal float
   int zc;                       // z-slab depth of one block
 };
 

@@ -855,6 +855,14 @@ struct RawX {
   uint16_t xl, ol;
 };
 
+// 1 / max(eps, sqrt(n2)).  Where eps^2 is a normal float, n2 > eps^2 is too, and the
+// hardware reciprocal square root gives the library's result without its denormal
+// scaling; otherwise the library routine handles the denormal range.
+__device__ __forceinline__ float inv_norm(const ProxArgs& a, float n2) {
+  if (a.eps2_normal) return n2 > a.eps * a.eps ? __builtin_amdgcn_rsqf(n2) : 1.0f / a.eps;
+  return n2 > a.eps * a.eps ? rsqrtf(n2) : 1.0f / a.eps;
+}
+
 template <bool COMP>
 __device__ __forceinline__ void fetch_raw(const ProxArgs& a, long long i, RawX& r) {
   r.xh = a.xk_hi[i];
@@ -996,7 +1004,7 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
       const float dzv = yc - sY[yp][ly + 1][lx + 1];
       // v / max(eps, |Dy|) with one reciprocal square root
       const float n2 = dxv * dxv + dyv * dyv + dzv * dzv;
-      const float inv = n2 > a.eps * a.eps ? rsqrtf(n2) : 1.0f / a.eps;
+      const float inv = inv_norm(a, n2);
       const float sc = vv[t] * inv;
       sP[dst][0][ly][lx] = sc * dzv;
       sP[dst][1][ly][lx] = sc * dyv;
@@ -1207,13 +1215,15 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
 
   auto slot3 = [](int zz) { return ((zz % 3) + 3) % 3; };
   auto pz_of = [&](int zz) { return (long long)(zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz)) * plane; };
+  // x_{k-1} words are read unconditionally (from x_k when the momentum term is off, where
+  // eval_raw ignores them), so that every load takes a block-uniform base
+  const float* __restrict__ xo_hi = a.read_old ? a.xo_hi : a.xk_hi;
+  const uint16_t* __restrict__ xo_lo = a.read_old ? a.xo_lo : a.xk_lo;
   auto fetch_one = [&](long long pz, unsigned o, RawX& w) {
     w.xh = ld_at(a.xk_hi + pz, o * 4u);
     if constexpr (COMP) w.xl = ld_at(a.xk_lo + pz, o * 2u);
-    if (a.read_old) {
-      w.oh = ld_at(a.xo_hi + pz, o * 4u);
-      if constexpr (COMP) w.ol = ld_at(a.xo_lo + pz, o * 2u);
-    }
+    w.oh = ld_at(xo_hi + pz, o * 4u);
+    if constexpr (COMP) w.ol = ld_at(xo_lo + pz, o * 2u);
   };
   auto ld_w = [&](const void* base, long long pz, unsigned o) -> float {
     const VT* b = reinterpret_cast<const VT*>(base) + pz;
@@ -1238,7 +1248,8 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
     }
   };
   auto fetch_out = [&](int zz, float* uu, float* xq) {
-    const long long pz = (long long)zz * plane;
+    long long pz = (long long)zz * plane;
+    asm volatile("" : "+s"(pz));
 #pragma unroll
     for (int h = 0; h < NO; ++h) {
       uu[h] = a.u ? ld_w(a.u, pz, own_off[h]) : 1.0f;
@@ -1247,12 +1258,28 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
     }
   };
   // spectrum rows of the batch starting at plane zb for the inverse half (row fr - NR)
+  // (block-uniform base at plane zb, tile row y0; per-thread 32-bit byte offsets)
+  auto row_off = [&](int row) { return (unsigned)(((row / TY) * ny + row % TY) * M + fq) * 8u; };
   auto fetch_spec = [&](int zb, float2* sr) {
     const int zz = zb + (fr - NR) / TY;
     if (fr >= NR && zz < z1) {
-      const float2* __restrict__ src = S + ((long long)zz * ny + y0 + (fr - NR) % TY) * M;
+      const float2* __restrict__ src = S + ((long long)zb * ny + y0) * M;
+      const unsigned o = row_off(fr - NR);
 #pragma unroll
-      for (int i = 0; i < FE; ++i) sr[i] = ld_at(src, (unsigned)(fq + FT * i) * 8u);
+      for (int i = 0; i < FE; ++i) sr[i] = ld_at(src, o + (unsigned)(FT * i) * 8u);
+    }
+  };
+  // y = x_k + m (x_k - x_{k-1}) as eval_raw, without its branch: with the momentum term
+  // off, m = 0 and the x_{k-1} words are x_k's, so y = x_k (up to the sign of a zero y,
+  // which no output depends on)
+  auto eval = [&](const RawX& w, double& y, double& xk) {
+    if constexpr (COMP) {
+      xk = (double)w.xh + (double)bf16_to_f32(w.xl);
+      const double xo = (double)w.oh + (double)bf16_to_f32(w.ol);
+      y = xk + a.m * (xk - xo);
+    } else {
+      y = w.xh + (float)a.m * (w.xh - w.oh);
+      xk = w.xh;
     }
   };
   // y of a plane into the ring; own y (fp64 in the compensated mode) and x_k kept
@@ -1261,13 +1288,13 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
 #pragma unroll
     for (int h = 0; h < NO; ++h) {
       double yv, xv;
-      eval_raw<COMP>(a, own[h], yv, xv);
+      eval(own[h], yv, xv);
       ys[h] = yv;
       xks[h] = xv;
       Y[r + 2 * h + 1][x] = (float)yv;
     }
     double yv, xv;
-    eval_raw<COMP>(a, halo, yv, xv);
+    eval(halo, yv, xv);
     Y[hly + 1][x] = (float)yv;
   };
   // sc = v / max(eps, |Dy|) at row ly of plane zz, column x (backward differences)
@@ -1279,7 +1306,7 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
     const float dyv = yc - Y[ly][x];
     const float dzv = yc - Yp[ly + 1][x];
     const float n2 = dxv * dxv + dyv * dyv + dzv * dzv;
-    const float inv = n2 > a.eps * a.eps ? rsqrtf(n2) : 1.0f / a.eps;
+    const float inv = inv_norm(a, n2);
     return vv * inv;
   };
   // writes the ring slot of plane zz and returns the thread's own values in sco
@@ -1316,23 +1343,21 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
         }
       }
     }
+    // point i of this thread is k = fq + FT i; its mirror M - k is element FT (FE - 1 - i)
+    // past mb (k = 0, only at fq = 0 and i = 0, reads the row's pad word and is replaced)
+    const int mb = M - fq - FT * (FE - 1);
     __syncthreads();
     // inverse half: Z[k] = E + i O from the row and its mirror (as k_c2r_x), conjugated
     if (act && !fwd) {
 #pragma unroll
       for (int i = 0; i < FE; ++i) {
-        const int k = fq + FT * i;
         const float2 xk = sa[i];
-        float2 zk;
-        if (k == 0) {
-          zk = make_float2(xk.x + xk.y, xk.x - xk.y);
-        } else {
-          const float2 xmr = make_float2(fre[M - k], fim[M - k]);
-          const float2 e = make_float2(xk.x + xmr.x, xk.y - xmr.y);
-          const float2 d = make_float2(xk.x - xmr.x, xk.y + xmr.y);
-          const float2 o = cmulc(d, s_twn[k]);
-          zk = make_float2(e.x - o.y, e.y + o.x);
-        }
+        const float2 xmr = make_float2(fre[mb + FT * (FE - 1 - i)], fim[mb + FT * (FE - 1 - i)]);
+        const float2 e = make_float2(xk.x + xmr.x, xk.y - xmr.y);
+        const float2 d = make_float2(xk.x - xmr.x, xk.y + xmr.y);
+        const float2 o = cmulc(d, s_twn[fq + FT * i]);
+        float2 zk = make_float2(e.x - o.y, e.y + o.x);
+        if (i == 0 && fq == 0) zk = make_float2(xk.x + xk.y, xk.x - xk.y);
         v[i] = make_float2(zk.x, -zk.y);
       }
     }
@@ -1354,22 +1379,18 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
     }
     __syncthreads();
     if (act && fwd) {
-      float2* __restrict__ dst = S + ((long long)zz * ny + y0 + row % TY) * M;
+      float2* __restrict__ dst = S + ((long long)zf * ny + y0) * M;
+      const unsigned ob = row_off(row);
 #pragma unroll
       for (int i = 0; i < FE; ++i) {
-        const int k = fq + FT * i;
         const float2 zk = v[i];
-        float2 out;
-        if (k == 0) {
-          out = make_float2(zk.x + zk.y, zk.x - zk.y);
-        } else {
-          const float2 zm = make_float2(fre[M - k], fim[M - k]);
-          const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-          const float2 d = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y + zm.y));
-          const float2 o = make_float2(d.y, -d.x);
-          out = cadd(e, cmul(s_twn[k], o));
-        }
-        st_at(dst, (unsigned)k * 8u, out);
+        const float2 zm = make_float2(fre[mb + FT * (FE - 1 - i)], fim[mb + FT * (FE - 1 - i)]);
+        const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+        const float2 d = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y + zm.y));
+        const float2 o = make_float2(d.y, -d.x);
+        float2 out = cadd(e, cmul(s_twn[fq + FT * i], o));
+        if (i == 0 && fq == 0) out = make_float2(zk.x + zk.y, zk.x - zk.y);
+        st_at(dst, ob + (unsigned)(FT * i) * 8u, out);
       }
     }
   };
@@ -1431,7 +1452,8 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
         const float(*Y1)[NX] = sY[slot3(z + 1)];
         const float(*SC0)[NX] = sSC[z & 1];
         float(*G)[NX] = sG[z - zb];
-        const long long pz = (long long)z * plane;
+        long long pz = (long long)z * plane;
+        asm volatile("" : "+s"(pz));
         float* __restrict__ xnh = a.xn_hi + pz;
         uint16_t* __restrict__ xnl = a.xn_lo + pz;
 #pragma unroll
