@@ -151,6 +151,33 @@ spg_status spg_get_penalty_weights(spg_problem* P, float* d_u_out, float* d_v_ou
  * not finite.  Leaves the iteration state unchanged. */
 spg_status spg_final_check(spg_problem* P, double* F_eps, double* F_0, double* kkt_rel);
 
+/* Scales for choosing the parameters (the paper's discussion of parameter choice, after
+ * eq 33): rms_unreg = the root mean square over voxels of the unregularised solution
+ * Re F^H (b [w > 0]) (F the unitary DFT of spg_set_data's convention), mean_w = the mean of
+ * the Fourier weights w = N(n).  Both are taken by spg_set_data in fp64 (by Parseval,
+ * rms_unreg^2 = sum_k |(b'(k) + conj b'(-k))/2|^2 / nvox with b' = b [w > 0]); this call
+ * reads them on the host and does no GPU work.  Either output may be NULL.  SPG_E_STATE
+ * before spg_set_data has succeeded. */
+spg_status spg_param_scales(const spg_problem* P, double* rms_unreg, double* mean_w);
+
+/* Parameters on those scales (same passage): lambda = rms_unreg * eps1 and
+ * mu = rms_unreg * eps2 (the l1 and TV weights scaled by the reweighting floors they are
+ * divided by), gamma = mean_w.  eps1, eps2 finite and > 0.  Host only; any output may be
+ * NULL.  The caller applies them with spg_set_params / spg_create. */
+spg_status spg_suggest_params(const spg_problem* P, double eps1, double eps2, double* lambda, double* mu,
+                              double* gamma);
+
+/* The log-penalty objective of eq 10, as a minimisation, at the current map x:
+ *   G(x) = 1/2 sum_k w_k |(F x)_k - b_k|^2 + lambda sum_i log(|x_i| + eps1)
+ *          + mu sum_i log(|(D x)_i|_2 + eps2),
+ * D the periodic backward differences of eq 12; the gamma term of eq 22 is not included.
+ * The reweighting of eq 11 replaces each logarithm by its tangent at the previous map, so
+ * rounds solved to convergence do not increase G (up to the smoothing of eq 14).  The data
+ * term is evaluated as in spg_final_check (fp32 transforms, fp64 accumulation); the
+ * penalty sums read the full iterate in fp64.  eps1, eps2 finite and > 0.  Synchronises;
+ * leaves the iteration state unchanged.  SPG_E_DIVERGED if G is not finite. */
+spg_status spg_log_objective(spg_problem* P, double eps1, double eps2, double* G);
+
 /* Checkpoint: bytes needed by spg_get_state, then copy the iteration state (current
  * and previous map, momentum counters, L, round) into / out of a caller device buffer.
  * Restoring into a problem with the same parameters, data and penalty weights gives

@@ -42,6 +42,9 @@ listed in the design notes):
       separate floors eps1 (l1) and eps2 (TV), using the unsmoothed |Dx|.
   R8  Ties: soft(z, t) = 0 at |z| = t; sign(0) = 0; both branches of eq 16
       agree at |Dx| = eps.
+  R13 Parameter scales (after eq 33): the unregularised solution is
+      Re A^H (b [w > 0]); its scale is the root mean square over voxels;
+      lam = scale * eps1, mu = scale * eps2, gamma = mean N(n).
 """
 from __future__ import annotations
 
@@ -314,3 +317,25 @@ def kkt_residual(x: np.ndarray, prob: Problem) -> float:
     tx = spg_step(x, prob, lr)
     nx = float(np.linalg.norm(x))
     return float(np.linalg.norm(x - tx)) / (nx if nx > 0 else 1.0)
+
+
+# ----------------------------------------------------------------------------
+# Parameter scales (the paper's discussion of parameter choice, after eq 33)
+# ----------------------------------------------------------------------------
+
+def param_scales(w: np.ndarray, b: np.ndarray):
+    """The two scales the paper sets the restraint parameters by: the root mean square over
+    voxels of the unregularised solution -- the inverse transform of the data where it is
+    weighted, Re A^H (b [w > 0]) (reading R13) -- and the mean of the weights N(n)."""
+    w = np.asarray(w, dtype=np.float64)
+    z = np.where(w > 0, np.asarray(b, dtype=np.complex128), 0.0)
+    x = ifft3(z).real
+    return float(np.sqrt(np.mean(x * x))), float(np.mean(w))
+
+
+def suggest_params(w: np.ndarray, b: np.ndarray, eps1: float, eps2: float):
+    """alpha and beta on the scale of the unregularised solution, multiplied by the floors
+    eps1, eps2 of the weighted norms they pair with; gamma on the scale of the mean N(n).
+    Returns (lam, mu, gamma)."""
+    rms, mean_w = param_scales(w, b)
+    return rms * eps1, rms * eps2, mean_w

@@ -134,6 +134,7 @@ struct spg_problem {
   bool sticky = false;
   bool unif_u = true, unif_v = true;
   double maxwt = 0, vmax = 1, C0 = 0, L = 0, lr = 0, dn2 = 12;
+  double rms_unreg = 0, mean_w = 0;  // parameter scales of the current data
   int cur = 0, old = 1;
   int64_t iters_done = 0;
   int32_t round = 1;
@@ -404,10 +405,10 @@ spg_status spg_set_data(spg_problem* P, const float* d_w, const float* d_b) {
   double* part = P->part();
   // 1. check the inputs before touching any state
   SPG_CK(P, launch_data_stats(d, d_w, b, part, kStatBlocks, P->stream));
-  const int ops3[3] = {RED_OP_SUM, RED_OP_MIN, RED_OP_SUM};
-  SPG_CK(P, launch_reduce(part, kStatBlocks, 3, ops3, P->res(), P->stream));
-  double r[3];
-  if ((s = read_results(P, r, 3))) return s;
+  const int ops5[5] = {RED_OP_SUM, RED_OP_MIN, RED_OP_SUM, RED_OP_SUM, RED_OP_SUM};
+  SPG_CK(P, launch_reduce(part, kStatBlocks, 5, ops5, P->res(), P->stream));
+  double r[5];
+  if ((s = read_results(P, r, 5))) return s;
   if (r[0] > 0) return set_err(P, SPG_E_NONFINITE, "w or b holds NaN/Inf values");
   if (r[1] < 0) return set_err(P, SPG_E_INVAL, "negative Fourier weight");
   // 2. fold onto the packed half spectrum
@@ -420,6 +421,8 @@ spg_status spg_set_data(spg_problem* P, const float* d_w, const float* d_b) {
   if ((s = read_results(P, &mx, 1))) return s;
   P->maxwt = mx;
   P->C0 = r[2];
+  P->mean_w = r[3] / (double)d.nvox;
+  P->rms_unreg = std::sqrt(r[4] / (double)d.nvox);
   P->data_set = true;
   recompute_L(P);
   restart(P);
@@ -632,6 +635,53 @@ spg_status spg_final_check(spg_problem* P, double* F_eps, double* F_0, double* k
   if (F_0) *F_0 = f0;
   if (kkt_rel) *kkt_rel = kkt;
   if (!std::isfinite(fe)) return set_err(P, SPG_E_DIVERGED, "objective is not finite");
+  return SPG_OK;
+}
+
+spg_status spg_param_scales(const spg_problem* P, double* rms_unreg, double* mean_w) {
+  if (!P) return SPG_E_INVAL;
+  if (!P->data_set) return SPG_E_STATE;
+  if (rms_unreg) *rms_unreg = P->rms_unreg;
+  if (mean_w) *mean_w = P->mean_w;
+  return SPG_OK;
+}
+
+spg_status spg_suggest_params(const spg_problem* P, double eps1, double eps2, double* lambda, double* mu,
+                              double* gamma) {
+  if (!P) return SPG_E_INVAL;
+  if (!std::isfinite(eps1) || !std::isfinite(eps2) || eps1 <= 0 || eps2 <= 0) return SPG_E_INVAL;
+  if (!P->data_set) return SPG_E_STATE;
+  if (lambda) *lambda = P->rms_unreg * eps1;
+  if (mu) *mu = P->rms_unreg * eps2;
+  if (gamma) *gamma = P->mean_w;
+  return SPG_OK;
+}
+
+spg_status spg_log_objective(spg_problem* P, double eps1, double eps2, double* G) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if (!G) return set_err(P, SPG_E_INVAL, "output pointer is NULL");
+  if (!std::isfinite(eps1) || !std::isfinite(eps2) || eps1 <= 0 || eps2 <= 0)
+    return set_err(P, SPG_E_INVAL, "eps1 and eps2 must be finite and > 0");
+  if (!P->data_set) return set_err(P, SPG_E_STATE, "spg_set_data has not succeeded");
+  // data term as in spg_final_check (fp32 transforms of the hi words, fp64 partials); the
+  // gradient it also forms goes to the spare ring slot
+  const int spare = 3 - P->cur - P->old;
+  P->primed = false;
+  if ((s = r2c(P, P->xhi(P->cur), false))) return s;
+  int nA = 0, nB = 0;
+  if ((s = gradient_pipeline(P, true, &nA, &nB, P->xhi(spare), false))) return s;
+  SPG_CK(P, launch_log_terms(P->d, P->xhi(P->cur), P->xlo(P->cur), eps1, eps2, P->comp, P->part() + kPartC,
+                             kStatBlocks, P->stream));
+  const int sum1[1] = {RED_OP_SUM};
+  const int sum2[2] = {RED_OP_SUM, RED_OP_SUM};
+  SPG_CK(P, launch_reduce(P->part() + kPartA, nA, 1, sum1, P->res() + 0, P->stream));
+  SPG_CK(P, launch_reduce(P->part() + kPartB, nB, 1, sum1, P->res() + 1, P->stream));
+  SPG_CK(P, launch_reduce(P->part() + kPartC, kStatBlocks, 2, sum2, P->res() + 2, P->stream));
+  double r[4];
+  if ((s = read_results(P, r, 4))) return s;
+  *G = P->C0 + r[0] + r[1] + P->prm.lambda * r[2] + P->prm.mu * r[3];
+  if (!std::isfinite(*G)) return set_err(P, SPG_E_DIVERGED, "log objective is not finite");
   return SPG_OK;
 }
 

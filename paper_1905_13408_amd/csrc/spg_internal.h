@@ -88,8 +88,13 @@ hipError_t launch_get_map(const Dims& d, const float* hi, const uint16_t* lo, fl
                           hipStream_t st);
 hipError_t launch_fold(const Dims& d, const float* w, const float2* b, float* ws, float* w0p, float* wnyq,
                        float2* cs, float2* c0p, float2* cnyq, double* partials, int nblocks, hipStream_t st);
+// partials: 5 x nblocks (non-finite count, min w, 1/2 sum w|b|^2, sum w, energy of the
+// real part of the unregularised solution)
 hipError_t launch_data_stats(const Dims& d, const float* w, const float2* b, double* partials, int nblocks,
                              hipStream_t st);
+// partials: 2 x nblocks, sum log(|x| + eps1) and sum log(|Dx| + eps2)
+hipError_t launch_log_terms(const Dims& d, const float* hi, const uint16_t* lo, double eps1, double eps2, bool comp,
+                            double* partials, int nblocks, hipStream_t st);
 hipError_t launch_weight_stats(const Dims& d, const float* a, double* partials, int nblocks, hipStream_t st);
 hipError_t launch_reweight(const Dims& d, const float* hi, const uint16_t* lo, void* u, void* v,
                            double eps1, double eps2, int store, double* partials, int nblocks,

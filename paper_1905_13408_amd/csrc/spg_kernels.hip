@@ -1625,12 +1625,16 @@ __global__ void __launch_bounds__(256) k_fold(Dims d, const float* __restrict__ 
   if (threadIdx.x == 0) partials[blockIdx.x] = r;
 }
 
-// Input checks and constants over the full arrays: count of non-finite w or b values,
-// min w, and 1/2 sum w |b|^2 (the constant of the data term).
-__global__ void __launch_bounds__(256) k_data_stats(long long n, const float* __restrict__ w,
+// Input checks and constants over the full arrays (FFT order, [kz][ky][kx]): count of
+// non-finite w or b values, min w, 1/2 sum w |b|^2 (the constant of the data term), sum w,
+// and sum |h(k)|^2 with h(k) = (b'(k) + conj b'(-k)) / 2, b' = b [w > 0]: by Parseval the
+// energy of Re F^H b' (unitary F), the unregularised solution whose scale guides the choice
+// of lambda and mu.
+__global__ void __launch_bounds__(256) k_data_stats(Dims d, const float* __restrict__ w,
                                                     const float2* __restrict__ b, double* __restrict__ partials) {
   __shared__ double s_red[8];
-  double bad = 0.0, mn = 1e300, c0 = 0.0;
+  double bad = 0.0, mn = 1e300, c0 = 0.0, sw = 0.0, eh = 0.0;
+  const long long n = d.nvox, plane = (long long)d.nx * d.ny;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const float wv = w[i];
     const float2 bv = b[i];
@@ -1639,6 +1643,17 @@ __global__ void __launch_bounds__(256) k_data_stats(long long n, const float* __
     else {
       mn = wv < mn ? wv : mn;
       c0 += 0.5 * (double)wv * ((double)bv.x * bv.x + (double)bv.y * bv.y);
+      sw += (double)wv;
+      const int kx = (int)(i % d.nx), ky = (int)((i / d.nx) % d.ny), kz = (int)(i / plane);
+      const long long j = (long long)((d.nz - kz) % d.nz) * plane + (long long)((d.ny - ky) % d.ny) * d.nx +
+                          (d.nx - kx) % d.nx;
+      const float wm = w[j];
+      const float2 bm = b[j];
+      const double px = wv > 0.f ? (double)bv.x : 0.0, py = wv > 0.f ? (double)bv.y : 0.0;
+      const bool mok = wm > 0.f && isfinite(bm.x) && isfinite(bm.y);
+      const double qx = mok ? (double)bm.x : 0.0, qy = mok ? (double)bm.y : 0.0;
+      const double hx = 0.5 * (px + qx), hy = 0.5 * (py - qy);
+      eh += hx * hx + hy * hy;
     }
   }
   const int nb = gridDim.x;
@@ -1648,6 +1663,10 @@ __global__ void __launch_bounds__(256) k_data_stats(long long n, const float* __
   if (threadIdx.x == 0) partials[nb + blockIdx.x] = r;
   r = block_reduce<RED_OP_SUM>(c0, s_red);
   if (threadIdx.x == 0) partials[2 * nb + blockIdx.x] = r;
+  r = block_reduce<RED_OP_SUM>(sw, s_red);
+  if (threadIdx.x == 0) partials[3 * nb + blockIdx.x] = r;
+  r = block_reduce<RED_OP_SUM>(eh, s_red);
+  if (threadIdx.x == 0) partials[4 * nb + blockIdx.x] = r;
 }
 
 // Penalty-weight checks: count of non-finite values, min and max.
@@ -1674,12 +1693,14 @@ __global__ void __launch_bounds__(256) k_weight_stats(long long n, const float* 
 
 // Reweighting of eq 11 from the current map: u = 1/(|x| + eps1), v = 1/(|Dx| + eps2),
 // with |Dx| the periodic backward-difference gradient norm of eq 12.  Partial: max v.
-template <bool COMP, bool BF>
+// LOGS: no weights written; partials sum log(|x| + eps1) and sum log(|Dx| + eps2), the
+// penalty terms of the log objective of eq 10 that the reweighting majorises.
+template <bool COMP, bool BF, bool LOGS = false>
 __global__ void __launch_bounds__(256) k_reweight(Dims d, const float* __restrict__ hi, const uint16_t* __restrict__ lo,
                                                   void* __restrict__ u, void* __restrict__ v, double eps1,
                                                   double eps2, double* __restrict__ partials) {
   __shared__ double s_red[8];
-  double mx = 0.0;
+  double mx = 0.0, l1 = 0.0, l2 = 0.0;
   const long long plane = (long long)d.nx * d.ny;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < d.nvox;
        i += (long long)gridDim.x * blockDim.x) {
@@ -1694,14 +1715,26 @@ __global__ void __launch_bounds__(256) k_reweight(Dims d, const float* __restric
     const double ddy = xc - load_x<COMP>(hi, lo, iym);
     const double ddz = xc - load_x<COMP>(hi, lo, izm);
     const double nrm = sqrt(ddx * ddx + ddy * ddy + ddz * ddz);
-    st_real<BF>(u, i, (float)(1.0 / (fabs(xc) + eps1)));
-    const float vf = (float)(1.0 / (nrm + eps2));
-    const float vv = BF ? bf16_to_f32(f32_to_bf16(vf)) : vf;  // max of the stored values
-    st_real<BF>(v, i, vf);
-    mx = (double)vv > mx ? (double)vv : mx;
+    if constexpr (LOGS) {
+      l1 += log(fabs(xc) + eps1);
+      l2 += log(nrm + eps2);
+    } else {
+      st_real<BF>(u, i, (float)(1.0 / (fabs(xc) + eps1)));
+      const float vf = (float)(1.0 / (nrm + eps2));
+      const float vv = BF ? bf16_to_f32(f32_to_bf16(vf)) : vf;  // max of the stored values
+      st_real<BF>(v, i, vf);
+      mx = (double)vv > mx ? (double)vv : mx;
+    }
   }
-  const double r = block_reduce<RED_OP_MAX>(mx, s_red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = r;
+  if constexpr (LOGS) {
+    double r = block_reduce<RED_OP_SUM>(l1, s_red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = r;
+    r = block_reduce<RED_OP_SUM>(l2, s_red);
+    if (threadIdx.x == 0) partials[gridDim.x + blockIdx.x] = r;
+  } else {
+    const double r = block_reduce<RED_OP_MAX>(mx, s_red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = r;
+  }
 }
 
 // ---------------------------------------------------------------- Fourier shell correlation
@@ -2235,7 +2268,7 @@ hipError_t launch_fold(const Dims& d, const float* w, const float2* b, float* ws
 
 hipError_t launch_data_stats(const Dims& d, const float* w, const float2* b, double* partials, int nblocks,
                              hipStream_t st) {
-  k_data_stats<<<nblocks, 256, 0, st>>>(d.nvox, w, b, partials);
+  k_data_stats<<<nblocks, 256, 0, st>>>(d, w, b, partials);
   return hipGetLastError();
 }
 
@@ -2249,6 +2282,13 @@ hipError_t launch_reweight(const Dims& d, const float* hi, const uint16_t* lo, v
   if (store == ST_COMP) k_reweight<true, false><<<nblocks, 256, 0, st>>>(d, hi, lo, u, v, eps1, eps2, partials);
   else if (store == ST_BF16) k_reweight<false, true><<<nblocks, 256, 0, st>>>(d, hi, lo, u, v, eps1, eps2, partials);
   else k_reweight<false, false><<<nblocks, 256, 0, st>>>(d, hi, lo, u, v, eps1, eps2, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_log_terms(const Dims& d, const float* hi, const uint16_t* lo, double eps1, double eps2, bool comp,
+                            double* partials, int nblocks, hipStream_t st) {
+  if (comp) k_reweight<true, false, true><<<nblocks, 256, 0, st>>>(d, hi, lo, nullptr, nullptr, eps1, eps2, partials);
+  else k_reweight<false, false, true><<<nblocks, 256, 0, st>>>(d, hi, lo, nullptr, nullptr, eps1, eps2, partials);
   return hipGetLastError();
 }
 

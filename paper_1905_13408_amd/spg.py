@@ -67,6 +67,9 @@ def lib() -> ctypes.CDLL:
         "spg_get_map": [P, P],
         "spg_get_penalty_weights": [P, P, P],
         "spg_final_check": [P, POINTER(c_double), POINTER(c_double), POINTER(c_double)],
+        "spg_param_scales": [P, POINTER(c_double), POINTER(c_double)],
+        "spg_suggest_params": [P, c_double, c_double, POINTER(c_double), POINTER(c_double), POINTER(c_double)],
+        "spg_log_objective": [P, c_double, c_double, POINTER(c_double)],
         "spg_state_size": [P, POINTER(c_size_t)],
         "spg_get_state": [P, P, c_size_t],
         "spg_set_state": [P, P, c_size_t],
@@ -235,6 +238,26 @@ class SPGSolver:
         fe, f0, kk = c_double(), c_double(), c_double()
         self._check(self._L.spg_final_check(self._h, byref(fe), byref(f0), byref(kk)))
         return fe.value, f0.value, kk.value
+
+    def param_scales(self):
+        """(rms of the unregularised solution Re F^H(b [w > 0]), mean Fourier weight), taken
+        by set_data (the paper's parameter-choice discussion, after eq 33)."""
+        rms, mw = c_double(), c_double()
+        self._check(self._L.spg_param_scales(self._h, byref(rms), byref(mw)))
+        return rms.value, mw.value
+
+    def suggest_params(self, eps1, eps2):
+        """(lambda, mu, gamma) on the data's scales: rms * eps1, rms * eps2, mean weight."""
+        lam, mu, gam = c_double(), c_double(), c_double()
+        self._check(self._L.spg_suggest_params(self._h, float(eps1), float(eps2), byref(lam), byref(mu),
+                                               byref(gam)))
+        return lam.value, mu.value, gam.value
+
+    def log_objective(self, eps1, eps2):
+        """The log-penalty objective of eq 10 (minimisation form, no gamma term) at the current map."""
+        g = c_double()
+        self._check(self._L.spg_log_objective(self._h, float(eps1), float(eps2), byref(g)))
+        return g.value
 
     def state_size(self) -> int:
         n = c_size_t(0)

@@ -106,6 +106,10 @@ def test_null_handles_are_rejected(L):
     assert L.spg_set_fusion(None, 1) == -1
     on = ctypes.c_int32(7)
     assert L.spg_get_fusion(None, ctypes.byref(on)) == -1 and on.value == 7
+    d = ctypes.c_double(5.0)
+    assert L.spg_param_scales(None, ctypes.byref(d), None) == -1 and d.value == 5.0
+    assert L.spg_suggest_params(None, ctypes.c_double(0.1), ctypes.c_double(0.1), None, None, None) == -1
+    assert L.spg_log_objective(None, ctypes.c_double(0.1), ctypes.c_double(0.1), ctypes.byref(d)) == -1
     assert b"NULL" in L.spg_last_error(None)
 
 

@@ -149,6 +149,40 @@ def test_final_check_matches_oracle():
     assert torch.equal(g.get_map(), h.get_map())
 
 
+@pytest.mark.parametrize("compensated", [True, False])
+def test_param_scales_and_log_objective_match_oracle(compensated):
+    shape = (16, 32, 64)
+    announce(f"parameter scales and log objective, compensated={compensated}")
+    w, b, u, v, x0 = _rand_inputs(shape, 23)
+    rng = np.random.default_rng(np.random.SeedSequence([23, 5]))
+    w[rng.random(shape) < 0.2] = 0.0  # unweighted frequencies drop out of the unregularised solution
+    lam, mu, eps, eps1, eps2 = 0.02, 0.05, 1e-2, 0.05, 0.02
+    g = gpu_solver(shape, w, b, lam, mu, eps, u=u, v=v, x0=x0, compensated=compensated)
+    rms, mean_w = g.param_scales()
+    orms, omean_w = O.param_scales(w, b)
+    print(f"rms {rms:.12e} vs {orms:.12e}; mean w {mean_w:.12e} vs {omean_w:.12e}", flush=True)
+    assert abs(rms - orms) <= 1e-9 * orms and abs(mean_w - omean_w) <= 1e-9 * omean_w
+    sl, sm, sg = g.suggest_params(0.1, 0.03)
+    assert (sl, sm, sg) == (rms * 0.1, rms * 0.03, mean_w)
+    g.run(20)
+    G = g.log_objective(eps1, eps2)
+    x = to_np(g.get_map()).astype(np.float64)
+    p = oracle_problem(w, b, lam, mu, eps)
+    oG = O.log_objective(x, p, eps1, eps2)
+    # scale of the terms (the log sums can be negative and cancel the data term)
+    d = O.D(x)
+    scale = (abs(O.log_objective(x, O.Problem(w=p.w, b=p.b, lam=0.0, mu=0.0, eps=eps), eps1, eps2)) +
+             lam * float(np.sum(np.abs(np.log(np.abs(x) + eps1)))) +
+             mu * float(np.sum(np.abs(np.log(np.sqrt(np.sum(d * d, axis=0)) + eps2)))))
+    print(f"log objective {G:.10e} vs {oG:.10e} (scale {scale:.3e})", flush=True)
+    assert abs(G - oG) <= 1e-6 * scale
+    # state unchanged: continuing equals an uninterrupted run
+    g.run(5)
+    h = gpu_solver(shape, w, b, lam, mu, eps, u=u, v=v, x0=x0, compensated=compensated)
+    h.run(25)
+    assert torch.equal(g.get_map(), h.get_map())
+
+
 # ------------------------------------------------------------------ properties
 
 def test_deterministic_bitwise():

@@ -351,6 +351,41 @@ def test_reweighting_decreases_log_objective_eq9():
         assert bb <= a + 1e-9
 
 
+# ------------------------------------- P10: parameter scales (after eq 33) --------
+
+def test_param_scales_closed_forms():
+    shape = (6, 8, 10)
+    nvox = 6 * 8 * 10
+    k = (1, 2, 3)
+    km = (-1 % 6, -2 % 8, -3 % 10)
+    # the unitary DFT of cos(2 pi k.r / n) is sqrt(nvox)/2 at +k and at -k, zero elsewhere
+    b = np.zeros(shape, dtype=complex)
+    b[k] += math.sqrt(nvox) / 2
+    b[km] += math.sqrt(nvox) / 2
+    w = np.full(shape, 2.0)
+    rms, mean_w = O.param_scales(w, b)
+    assert abs(rms - 1 / math.sqrt(2)) < 1e-12 and mean_w == 2.0
+    # no weight at +k: the unregularised solution keeps the -k half, whose real part is cos / 2
+    w0 = w.copy()
+    w0[k] = 0.0
+    rms, mean_w = O.param_scales(w0, b)
+    assert abs(rms - 1 / (2 * math.sqrt(2))) < 1e-12
+    assert abs(mean_w - 2.0 * (nvox - 1) / nvox) < 1e-15
+    # i sqrt(nvox)/2 at +k with its conjugate at -k is -sin: the same scale
+    bs = np.zeros(shape, dtype=complex)
+    bs[k] = 1j * math.sqrt(nvox) / 2
+    bs[km] = -1j * math.sqrt(nvox) / 2
+    assert abs(O.param_scales(w, bs)[0] - 1 / math.sqrt(2)) < 1e-12
+    # a constant map c is sqrt(nvox) c at the DC term; a purely imaginary DC datum has no real part
+    bc = np.zeros(shape, dtype=complex)
+    bc[0, 0, 0] = -0.7 * math.sqrt(nvox)
+    assert abs(O.param_scales(w, bc)[0] - 0.7) < 1e-12
+    bc[0, 0, 0] = 3j
+    assert O.param_scales(w, bc)[0] < 1e-15
+    lam, mu, gamma = O.suggest_params(w, b, 0.1, 0.03)
+    assert abs(lam - 0.1 / math.sqrt(2)) < 1e-12 and abs(mu - 0.03 / math.sqrt(2)) < 1e-12 and gamma == 2.0
+
+
 # --------------------------------------------------- P9: symmetries -------------
 
 def test_sign_and_shift_equivariance():
