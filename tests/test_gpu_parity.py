@@ -199,6 +199,26 @@ def test_deterministic_bitwise():
     assert torch.equal(outs[0], outs[1])
 
 
+def test_periodic_shift_equivariance():
+    # shifting the map by s multiplies its spectrum by exp(-2 pi i k.s/n); with b, u, v and x0
+    # shifted alike (w unchanged) the iterates are the shifted iterates
+    shape = (16, 32, 64)
+    sft = (3, -5, 7)
+    announce(f"shift equivariance {sft}")
+    w, b, u, v, x0 = _rand_inputs(shape, 29)
+    kz, ky, kx = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    phase = np.exp(-2j * np.pi * (kz * sft[0] / shape[0] + ky * sft[1] / shape[1] + kx * sft[2] / shape[2]))
+    roll = lambda a: np.roll(a, sft, axis=(0, 1, 2))
+    lam, mu, eps = 0.02, 0.05, 1e-2
+    g1 = gpu_solver(shape, w, b, lam, mu, eps, u=u, v=v, x0=x0)
+    g1.run(30)
+    g2 = gpu_solver(shape, w, (b * phase).astype(np.complex64), lam, mu, eps, u=roll(u), v=roll(v), x0=roll(x0))
+    g2.run(30)
+    err = rel_l2(to_np(g2.get_map()), roll(to_np(g1.get_map())))
+    print(f"shift equivariance: rel L2 = {err:.3e}", flush=True)
+    assert err < TOL
+
+
 def test_checkpoint_resume_bitwise():
     shape = (16, 32, 64)
     announce("checkpoint / resume")

@@ -351,6 +351,35 @@ def test_reweighting_decreases_log_objective_eq9():
         assert bb <= a + 1e-9
 
 
+# ------------------------------------- P11: the fold of the data term (a0) ---------
+
+def test_fold_identity_with_nonsymmetric_weights():
+    # Re A^H(w (A x - b)) = A^H(w~ A x - c) with w~_k = (w_k + w_-k)/2 and
+    # c_k = (w_k b_k + w_-k conj b_-k)/2: the identity that lets the data gradient of a real
+    # map use only the half spectrum; w is deliberately not symmetric.
+    r = _rng(31)
+    shape = (6, 4, 8)
+    w = r.uniform(0.0, 2.0, size=shape)
+    b = r.standard_normal(shape) + 1j * r.standard_normal(shape)
+    x = r.standard_normal(shape)
+    lhs = O.ifft3(w * (O.fft3(x) - b)).real
+    wn = np.empty_like(w)
+    bn = np.empty_like(b)
+    for kz in range(shape[0]):          # the partner index -k written out, not via a helper
+        for ky in range(shape[1]):
+            for kx in range(shape[2]):
+                m = ((-kz) % shape[0], (-ky) % shape[1], (-kx) % shape[2])
+                wn[kz, ky, kx] = w[m]
+                bn[kz, ky, kx] = b[m]
+    wf = 0.5 * (w + wn)
+    c = 0.5 * (w * b + wn * np.conj(bn))
+    rhs = O.ifft3(wf * O.fft3(x) - c)
+    assert np.max(np.abs(rhs.imag)) < 1e-12
+    np.testing.assert_allclose(rhs.real, lhs, atol=1e-12)
+    np.testing.assert_allclose(O.fold_weights(w), wf, atol=0)
+    assert np.max(np.abs(O.ifft3(w * (O.fft3(x) - b)).imag)) > 1e-3  # w asymmetric: the plain form is complex
+
+
 # ------------------------------------- P10: parameter scales (after eq 33) --------
 
 def test_param_scales_closed_forms():
