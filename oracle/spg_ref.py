@@ -60,10 +60,16 @@ __all__ = [
     "Problem", "fft3", "ifft3", "D", "DT", "huber", "soft", "fold_weights",
     "dnorm2", "lipschitz", "grad_data", "tv_dual", "grad_tv", "grad_smooth",
     "objective", "spg_step", "fista_momenta", "spg_solve", "reweight",
-    "solve_schedule", "kkt_residual", "log_objective",
+    "solve_schedule", "kkt_residual", "log_objective", "param_scales", "suggest_params", "fft_workers",
 ]
 
 _WORKERS = max(1, len(os.sched_getaffinity(0))) if hasattr(os, "sched_getaffinity") else 1
+
+
+def fft_workers() -> int:
+    """Threads scipy.fft uses here (the process's CPU affinity); the rest of the oracle is
+    single-threaded NumPy."""
+    return _WORKERS
 
 
 # ----------------------------------------------------------------------------
