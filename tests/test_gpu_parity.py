@@ -264,6 +264,10 @@ def test_input_validation_on_device():
     with pytest.raises(spg.SPGError) as e:
         s.run(1)
     assert e.value.status == -4
+    for call in (s.param_scales, lambda: s.suggest_params(0.1, 0.1), lambda: s.log_objective(0.1, 0.1)):
+        with pytest.raises(spg.SPGError) as e:
+            call()
+        assert e.value.status == -4
     wb = w.copy()
     wb[1, 2, 3] = np.nan
     with pytest.raises(spg.SPGError) as e:
@@ -283,6 +287,11 @@ def test_input_validation_on_device():
     with pytest.raises(spg.SPGError) as e:
         s.reweight(0.0, 0.1)
     assert e.value.status == -1
+    for call in (lambda: s.suggest_params(0.0, 0.1), lambda: s.log_objective(0.1, -1.0),
+                 lambda: s.log_objective(float("nan"), 0.1)):
+        with pytest.raises(spg.SPGError) as e:
+            call()
+        assert e.value.status == -1
     s.run(2)  # the problem is still usable after rejected calls
 
 
