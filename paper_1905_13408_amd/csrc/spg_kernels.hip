@@ -451,6 +451,20 @@ template <typename V>
 __device__ __forceinline__ void st_at(V* __restrict__ base, unsigned boff, V v) {
   *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + boff) = v;
 }
+// st_at, or (NT) a streaming (non-temporal) vector store: for outputs written once per
+// pass over a map too large for the caches, read back only by a later pass.
+template <bool NT, typename V>
+__device__ __forceinline__ void st_nt(V* __restrict__ base, unsigned boff, V v) {
+  char* p = reinterpret_cast<char*>(base) + boff;
+  if constexpr (!NT)
+    *reinterpret_cast<V*>(p) = v;
+  else if constexpr (sizeof(V) == 8)
+    __builtin_nontemporal_store(__builtin_bit_cast(unsigned long long, v), reinterpret_cast<unsigned long long*>(p));
+  else if constexpr (sizeof(V) == 4)
+    __builtin_nontemporal_store(__builtin_bit_cast(unsigned int, v), reinterpret_cast<unsigned int*>(p));
+  else
+    __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, v), reinterpret_cast<unsigned short*>(p));
+}
 
 template <int L, int MODE>
 __global__ void __launch_bounds__(16 * ColT<L>::T) k_fft_cols(float2* __restrict__ S, int P, int ntiles,
@@ -1168,8 +1182,10 @@ struct PfT {  // threads per row of the M-point complex transforms
   static constexpr int E = M / T;
 };
 
-// PRIOR: the gamma term's previous map is given (else it is 0).
-template <int NX, int ST, bool PRIOR>
+// PRIOR: the gamma term's previous map is given (else it is 0).  NT: x_{k+1} and the
+// spectrum rows go out by streaming stores (maps whose spectrum outgrows the last-level
+// cache; smaller maps are read back by the next pass while still cached).
+template <int NX, int ST, bool PRIOR, bool NT>
 __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restrict__ S,
                                                      const float2* __restrict__ twm,
                                                      const float2* __restrict__ twn, int nty) {
@@ -1390,7 +1406,7 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
         const float2 o = make_float2(d.y, -d.x);
         float2 out = cadd(e, cmul(s_twn[fq + FT * i], o));
         if (i == 0 && fq == 0) out = make_float2(zk.x + zk.y, zk.x - zk.y);
-        st_at(dst, ob + (unsigned)(FT * i) * 8u, out);
+        st_nt<NT>(dst, ob + (unsigned)(FT * i) * 8u, out);
       }
     }
   };
@@ -1482,8 +1498,8 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
             const double xn = az > 0.0 ? copysign(az, zv) : 0.0;
             const float hi = (float)xn;
             const uint16_t lo = f32_to_bf16((float)(xn - (double)hi));
-            st_at(xnh, own_off[h] * 4u, hi);
-            st_at(xnl, own_off[h] * 2u, lo);
+            st_nt<NT>(xnh, own_off[h] * 4u, hi);
+            st_nt<NT>(xnl, own_off[h] * 2u, lo);
             const double xs = (double)hi + (double)bf16_to_f32(lo);
             ynext = (float)(xs + a.m_next * (xs - own_xk[h]));
           } else {
@@ -1493,7 +1509,7 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
             const float t = (float)a.lr * (float)a.lam * uu;
             const float az = fabsf(zv) - t;
             const float xn = az > 0.f ? copysignf(az, zv) : 0.f;
-            st_at(xnh, own_off[h] * 4u, xn);
+            st_nt<NT>(xnh, own_off[h] * 4u, xn);
             const float xk = (float)own_xk[h];
             ynext = xn + (float)a.m_next * (xn - xk);
           }
@@ -2204,9 +2220,14 @@ hipError_t launch_prox_fft(const Dims& d, const ProxArgs& a, float2* S, const fl
   const long long nblk = (long long)nty * ((d.nz + a.zc - 1) / a.zc);
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 grid((unsigned)nblk), block(2 * d.nx);
-#define SPG_PF2(NX_, ST_)                                                             \
-  if (a.xprev) k_prox_fft<NX_, ST_, true><<<grid, block, 0, st>>>(a, S, tw_m, tw_n, nty); \
-  else k_prox_fft<NX_, ST_, false><<<grid, block, 0, st>>>(a, S, tw_m, tw_n, nty);
+  // Streaming stores pay where the spectrum alone (4 bytes per voxel) outgrows the 256 MiB
+  // last-level cache (measured at 512^3); smaller maps are read back by the next pass while
+  // still cached (measured on the batch of 128^3-256^3 maps).
+  const bool stream = (double)d.nvox * 4.0 >= 256.0 * 1024 * 1024;
+#define SPG_PF2(NX_, ST_)                                                                          \
+  if (a.xprev) k_prox_fft<NX_, ST_, true, false><<<grid, block, 0, st>>>(a, S, tw_m, tw_n, nty);      \
+  else if (stream) k_prox_fft<NX_, ST_, false, true><<<grid, block, 0, st>>>(a, S, tw_m, tw_n, nty);     \
+  else k_prox_fft<NX_, ST_, false, false><<<grid, block, 0, st>>>(a, S, tw_m, tw_n, nty);
 #define SPG_PF(NX_)                                   \
   switch (store) {                                    \
     case ST_PLAIN: SPG_PF2(NX_, ST_PLAIN); break;     \
