@@ -1231,8 +1231,8 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
 
   auto slot3 = [](int zz) { return ((zz % 3) + 3) % 3; };
   auto pz_of = [&](int zz) { return (long long)(zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz)) * plane; };
-  // x_{k-1} words are read unconditionally (from x_k when the momentum term is off, where
-  // eval_raw ignores them), so that every load takes a block-uniform base
+  // x_{k-1} words are read unconditionally (from x_k when the momentum term is off: m = 0
+  // then and y = x_k), so that every load takes a block-uniform base
   const float* __restrict__ xo_hi = a.read_old ? a.xo_hi : a.xk_hi;
   const uint16_t* __restrict__ xo_lo = a.read_old ? a.xo_lo : a.xk_lo;
   auto fetch_one = [&](long long pz, unsigned o, RawX& w) {
