@@ -188,8 +188,8 @@ spg_status spg_set_state(spg_problem* P, const void* d_buf, size_t bytes);
 
 /* Launch shapes: columns per tile of the y and z transform passes (8 or 16) and the z-slab
  * depth of the stencil kernel (4..512 planes).  spg_autotune times each knob in turn
- * (coordinate search over {16, 8}, {16, 8}, fused x transforms {on, off} where the grid
- * supports them (see spg_set_fusion), {32, 16, 64, 128, 256}) on `iters` iterations (after three
+ * (coordinate search over {16, 8}, {16, 8}, fused x transforms {on, off} when they are on
+ * (see spg_set_fusion), {32, 16, 64, 128, 256}) on `iters` iterations (after three
  * untimed ones, so that the momentum term is active) from the zero map, with the penalty
  * weights as set, with HIP events, and keeps the fastest; it leaves the map at 0 with the
  * momentum restarted.  Results are bitwise independent of the launch shape. */
@@ -206,7 +206,8 @@ spg_status spg_autotune(spg_problem* P, int32_t iters);
  * same operations; the prox of the compensated mode is fp64 in both).  With
  * SPG_FLAG_BF16_STORAGE the fused path keeps the gradient and extrapolated rows in fp32.
  * spg_set_fusion(P, 1) on a grid without support returns SPG_E_UNSUPPORTED; 0 selects
- * the separate sweeps.  Iterations of spg_run_checkpointed always use the separate sweeps
+ * the separate sweeps, which spg_autotune then keeps (it may turn the fused path off where
+ * the separate sweeps measure faster, never on).  Iterations of spg_run_checkpointed always use the separate sweeps
  * (they keep the data gradient of every iteration). */
 spg_status spg_set_fusion(spg_problem* P, int32_t enable);
 spg_status spg_get_fusion(const spg_problem* P, int32_t* enabled);

@@ -827,8 +827,8 @@ spg_status spg_autotune(spg_problem* P, int32_t iters) {
   if (P->prof_on) return set_err(P, SPG_E_STATE, "profiling is active");
   // coordinate search: for each knob, time the kernel classes it changes over `iters`
   // iterations from the zero map for every candidate and keep the fastest.  The fusion
-  // knob (where the grid supports it) compares the fused stencil/prox kernel with the
-  // stencil kernel plus the separate x-axis sweeps.
+  // knob (where the fused path is on) compares the fused stencil/prox kernel with the
+  // stencil kernel plus the separate x-axis sweeps; a path set off stays off.
   struct Knob {
     int* val;
     std::vector<int> cls;
@@ -837,8 +837,7 @@ spg_status spg_autotune(spg_problem* P, int32_t iters) {
   int fused = P->fused ? 1 : 0;
   std::vector<Knob> knobs = {{&P->nt_y, {SPG_KERNEL_FFT_Y_FWD}, {16, 8}},
                              {&P->nt_z, {SPG_KERNEL_FFT_Z_WEIGHT}, {16, 8}}};
-  if (prox_fft_supported(P->d))
-    knobs.push_back({&fused, {SPG_KERNEL_PROX_TV, SPG_KERNEL_C2R_X, SPG_KERNEL_R2C_X}, {1, 0}});
+  if (P->fused) knobs.push_back({&fused, {SPG_KERNEL_PROX_TV, SPG_KERNEL_C2R_X, SPG_KERNEL_R2C_X}, {1, 0}});
   knobs.push_back({&P->zc, {SPG_KERNEL_PROX_TV}, {32, 16, 64, 128, 256}});
   for (Knob& kb : knobs) {
     int best = *kb.val;

@@ -542,6 +542,10 @@ def test_autotune_picks_candidates_and_resets():
     h.set_fusion(g.fusion)  # the tuner may pick either x-transform path; shapes do not change results
     h.run(10)
     assert torch.equal(g.get_map(), h.get_map())
+    k = gpu_solver(shape, w, b, 0.02, 0.05, 1e-2)
+    k.set_fusion(False)  # a path the caller turned off stays off
+    k.autotune(2)
+    assert not k.fusion
 
 
 def _batch_members(seed):
