@@ -194,7 +194,7 @@ def bench_batch(args):
     for shape, vol, lam, mu in members:
         sv = spg.SPGSolver(shape, lam, mu, 1e-3, storage=args.storage)
         sv.set_data(torch.from_numpy(vol.w).cuda(), torch.from_numpy(vol.b).cuda())
-        shapes_tuned.append(list(sv.autotune(3) if not args.no_autotune else sv.launch_shape()) + [sv.fusion])
+        shapes_tuned.append(list(sv.autotune(8) if not args.no_autotune else sv.launch_shape()) + [sv.fusion])
         solvers.append(sv)
     batch = spg.SPGBatch(solvers)
     vox_it = sum(int(sh[0]) ** 3 for sh, _, _, _ in members) * iters
@@ -299,7 +299,7 @@ def main():
         solver.set_launch_shape(*args.launch_shape)
         launch_shape = solver.launch_shape()
     else:
-        launch_shape = solver.launch_shape() if args.no_autotune else solver.autotune(3)
+        launch_shape = solver.launch_shape() if args.no_autotune else solver.autotune(8)
     del ones
     if args.no_fusion:
         solver.set_fusion(False)
