@@ -23,9 +23,12 @@ KERNEL_SOURCE = os.path.join(HERE, "csrc", "spg_kernels.hip")
 # kernel-name prefixes (rocprofv3 names) -> kernel classes of the solver
 CLASSES = [
     ("spg::k_fft_cols<512, 0>", "fft_y_fwd"), ("spg::k_fft_cols<512, 1>", "fft_y_inv"),
-    ("spg::k_fft_zw<512, 2>", "fft_z_weight"), ("spg::k_dc_nyquist<512, false>", "dc_nyquist"),
+    ("spg::k_fft_zw<512, 2,", "fft_z_weight"), ("spg::k_dc_nyquist<512, false>", "dc_nyquist"),
     ("spg::k_c2r_x<256", "c2r_x"), ("spg::k_r2c_x<256", "r2c_x"), ("spg::k_prox_tv<", "prox_tv"),
 ]
+# a trailing "true>" marks an objective/check instance of these kernels (not an iteration
+# launch), except in the z pass, where it marks the streaming-load variant
+KEEP_TRUE = ("spg::k_fft_zw<",)
 
 
 FUSED = "spg::k_prox_fft<"  # stencil/prox kernel with the x-axis transforms inside
@@ -65,8 +68,11 @@ def summarize(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, 
     fa, wa = _per_kernel(fetch_csv), _per_kernel(write_csv)
     out = {}
     for prefix, cls in CLASSES:
-        fv = [v for k, lst in fa.items() if k.startswith(prefix) and "true>" not in k[len(prefix):] for v in lst]
-        wv = [v for k, lst in wa.items() if k.startswith(prefix) and "true>" not in k[len(prefix):] for v in lst]
+        keep = prefix.startswith(KEEP_TRUE)
+        fv = [v for k, lst in fa.items() if k.startswith(prefix) and (keep or "true>" not in k[len(prefix):])
+              for v in lst]
+        wv = [v for k, lst in wa.items() if k.startswith(prefix) and (keep or "true>" not in k[len(prefix):])
+              for v in lst]
         if cls == "prox_tv":
             # iteration launches only: the fused kernel where it ran, else the stencil kernel
             # outside its check mode (another instance)
