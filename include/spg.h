@@ -207,8 +207,10 @@ spg_status spg_autotune(spg_problem* P, int32_t iters);
  * SPG_FLAG_BF16_STORAGE the fused path keeps the gradient and extrapolated rows in fp32.
  * spg_set_fusion(P, 1) on a grid without support returns SPG_E_UNSUPPORTED; 0 selects
  * the separate sweeps, which spg_autotune then keeps (it may turn the fused path off where
- * the separate sweeps measure faster, never on).  Iterations of spg_run_checkpointed always use the separate sweeps
- * (they keep the data gradient of every iteration). */
+ * the separate sweeps measure faster, never on).  Iterations of spg_run_checkpointed and the
+ * replays of spg_vjp always use the separate sweeps (the replays keep the data gradient of
+ * every iteration), so that the recorded and replayed trajectories agree bitwise; the
+ * setting is restored afterwards. */
 spg_status spg_set_fusion(spg_problem* P, int32_t enable);
 spg_status spg_get_fusion(const spg_problem* P, int32_t* enabled);
 

@@ -276,8 +276,10 @@ def fista_momenta(K: int) -> np.ndarray:
 
 
 def spg_solve(prob: Problem, K: int, x0: Optional[np.ndarray] = None, accel: bool = True,
-              lr: Optional[float] = None, history: Optional[list] = None) -> np.ndarray:
-    """K SPG iterations from x0 (default 0) with momentum restarted at x_{-1} = x_0."""
+              lr: Optional[float] = None, history: Optional[list] = None, callback=None) -> np.ndarray:
+    """K SPG iterations from x0 (default 0) with momentum restarted at x_{-1} = x_0.
+
+    ``callback(k, x)``, if given, sees the iterate after iteration k = 1..K (read only)."""
     x = np.zeros(prob.shape) if x0 is None else np.array(x0, dtype=np.float64)
     x_old = x.copy()
     if lr is None:
@@ -289,6 +291,8 @@ def spg_solve(prob: Problem, K: int, x0: Optional[np.ndarray] = None, accel: boo
         x_old, x = x, x_new
         if history is not None:
             history.append(objective(x, prob))
+        if callback is not None:
+            callback(k + 1, x)
     return x
 
 
@@ -301,18 +305,24 @@ def reweight(x: np.ndarray, eps1: float, eps2: float):
     return 1.0 / (np.abs(x) + eps1), 1.0 / (n + eps2)
 
 
-def solve_schedule(prob: Problem, rounds: int, iters: int, eps1: float, eps2: float,
-                   x0: Optional[np.ndarray] = None, accel: bool = True):
+def solve_schedule(prob: Problem, rounds: int, iters, eps1: float, eps2: float,
+                   x0: Optional[np.ndarray] = None, accel: bool = True, callback=None):
     """Reweighting outer loop: round 1 uses the problem's u, v; before each later
     round u, v are recomputed from the last x (eq 11), L is recomputed and the
-    momentum restarts from the last x.  Returns (x, u, v) after the last round."""
+    momentum restarts from the last x.  Returns (x, u, v) after the last round.
+
+    ``iters`` is one count for every round or a sequence of per-round counts.
+    ``callback(r, k, x, p)``, if given, sees round r (0-based), iteration k and the
+    round's problem (with its u, v) after every iteration (read only)."""
     p = replace(prob)
     x = np.zeros(prob.shape) if x0 is None else np.array(x0, dtype=np.float64)
+    counts = [int(iters)] * rounds if np.ndim(iters) == 0 else [int(k) for k in iters]
     for r in range(rounds):
         if r > 0:
             u, v = reweight(x, eps1, eps2)
             p = replace(p, u=u, v=v)
-        x = spg_solve(p, iters, x0=x, accel=accel)
+        cb = None if callback is None else (lambda k, xx, r=r, p=p: callback(r, k, xx, p))
+        x = spg_solve(p, counts[r], x0=x, accel=accel, callback=cb)
     return x, p.u, p.v
 
 

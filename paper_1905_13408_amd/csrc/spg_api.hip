@@ -1206,12 +1206,19 @@ spg_status spg_run_checkpointed(spg_problem* P, int32_t K, int32_t C, void* d_vj
   if ((s = ck_copy(P, ws, L, 0, true))) return s;
   P->old = (P->cur + 1) % 3;
   P->vjp_m.assign(K, 0.0);
-  for (int it = 0; it < K; ++it) {
-    if (it > 0 && it % C == 0)
-      if ((s = ck_copy(P, ws, L, it / C, true))) return s;
-    P->vjp_m[it] = P->m_cur;
-    if ((s = iterate_once(P, nullptr))) return s;
+  // the recorded iterations run the separate x-axis sweeps, as the replays of spg_vjp do
+  // (they keep the data gradient of every iteration), so that forward and replay agree bitwise
+  const bool fused = P->fused;
+  P->fused = false;
+  for (int it = 0; it < K && s == SPG_OK; ++it) {
+    if (it > 0 && it % C == 0) s = ck_copy(P, ws, L, it / C, true);
+    if (s == SPG_OK) {
+      P->vjp_m[it] = P->m_cur;
+      s = iterate_once(P, nullptr);
+    }
   }
+  P->fused = fused;
+  if (s) return s;
   if ((s = ck_copy(P, ws, L, L.nseg, true))) return s;
   P->vjp_valid = true;
   P->vjp_K = K;
