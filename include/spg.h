@@ -55,7 +55,7 @@ typedef enum {
   SPG_E_DEVICE = -3,      /* a HIP call failed; the problem is unusable             */
   SPG_E_STATE = -4,       /* call out of order (e.g. run before set_data)           */
   SPG_E_NONFINITE = -5,   /* non-finite value in w, b, u or v                       */
-  SPG_E_DIVERGED = -6,    /* non-finite objective found by spg_final_check          */
+  SPG_E_DIVERGED = -6,    /* non-finite objective (spg_final_check, the monitor)    */
   SPG_E_UNSUPPORTED = -7  /* valid request this build does not implement            */
 } spg_status;
 
@@ -68,6 +68,11 @@ typedef struct spg_problem spg_problem;   /* opaque, owned by the library */
 #define SPG_FLAG_BF16_STORAGE 2  /* fp32 iterate, but the penalty weights u, v and the
                                     gradient / extrapolated map are stored in bf16 (fp32
                                     arithmetic); excludes SPG_FLAG_COMPENSATED             */
+#define SPG_FLAG_MONITOR 4       /* objective monitor: every obj_every-th iteration of a round
+                                    also evaluates the smoothed objective F_eps (eq 31 with
+                                    eq 14) at its extrapolated point y_k, from fp64 partials
+                                    of the z pass (data term) and of the stencil kernel
+                                    (penalty terms); see spg_objective_history             */
 
 typedef struct {
   int32_t nx, ny, nz;   /* grid; each a power of two in [4, 512], or 160 or 192        */
@@ -77,6 +82,9 @@ typedef struct {
   double gamma;         /* implicit-descent weight of eq 22 (paper gamma), >= 0         */
   int32_t accel;        /* 1: FISTA momentum (default); 0: un-accelerated eq 20-21      */
   int32_t flags;        /* SPG_FLAG_* bits                                              */
+  int32_t obj_every;    /* >= 1 with SPG_FLAG_MONITOR: monitor iterations j of a round with
+                           j % obj_every == 0 (j = 1, 2, ... since the last momentum
+                           restart); >= 0 and unused otherwise                          */
 } spg_params;
 
 typedef struct {
@@ -85,6 +93,9 @@ typedef struct {
   int32_t iter_in_round;/* iterations since the last momentum restart                    */
   double lr;            /* current step 1/L                                              */
   double L;             /* current Lipschitz bound                                       */
+  double obj_smoothed;  /* SPG_FLAG_MONITOR: F_eps(y_k) of the last monitored iteration  */
+                        /* (NaN before the first one, and without the flag)             */
+  int64_t obj_iter;     /* its iteration number k (counted as iters_done), 0 if none     */
 } spg_stats;
 
 /* Bytes of device workspace a problem with these parameters needs (host only,
@@ -93,8 +104,10 @@ spg_status spg_workspace_size(const spg_params* p, size_t* bytes);
 
 /* Create a problem whose state lives in d_workspace (>= spg_workspace_size bytes,
  * 256-byte aligned, device memory that the caller frees after spg_destroy).
- * hip_stream is a hipStream_t (NULL = the default stream).  Uploads FFT twiddle
- * tables (computed in fp64 on the host) and synchronises the stream once. */
+ * hip_stream is a hipStream_t (NULL = the default stream).  Host only: the first later
+ * call that enqueues work uploads the FFT twiddle tables (computed in fp64 on the host),
+ * sets x_0 = 0 and synchronises the stream once; if that fails, that call and every later
+ * one return SPG_E_DEVICE. */
 spg_status spg_create(const spg_params* p, void* d_workspace, size_t bytes, void* hip_stream,
                       spg_problem** out);
 
@@ -127,8 +140,20 @@ spg_status spg_set_prior(spg_problem* P, double gamma, const float* d_xprev);
 spg_status spg_set_map(spg_problem* P, const float* d_x0);
 
 /* Run K >= 0 SPG iterations (eq 20-21 with momentum) on the stream.  Does not
- * synchronise.  opt_stats (may be NULL) receives the counters after the launches. */
+ * synchronise, except that with SPG_FLAG_MONITOR and opt_stats given it waits for the
+ * last monitored objective (8 bytes) and returns SPG_E_DIVERGED if it is not finite.
+ * opt_stats (may be NULL) receives the counters after the launches. */
 spg_status spg_run(spg_problem* P, int32_t K, spg_stats* opt_stats);
+
+/* The objective monitor (SPG_FLAG_MONITOR, section 2 eq 14 and eq 31): the n most recent
+ * monitored values F_eps(y_k) = 1/2 sum w |A y_k - b|^2 + lambda sum u |y_k|
+ * + mu sum v phi_eps(|D y_k|) + gamma |y_k - x_prev|^2 (fp32 transforms and stencil, fp64
+ * sums in a fixed order) with their iteration numbers k, oldest first, into host arrays of
+ * `cap` entries (either may be NULL when cap > 0 names the other); n = min(cap, entries
+ * so far, 4096) into *n_out.  The library keeps the last 4096 entries since spg_create.
+ * Synchronises the stream. */
+spg_status spg_objective_history(spg_problem* P, double* h_values, int64_t* h_iters, int32_t cap,
+                                 int32_t* n_out);
 
 /* Reweight (eq 11): u = 1/(|x| + eps1), v = 1/(|Dx|_2 + eps2) from the current map,
  * then recompute L and restart the momentum.  eps1, eps2 > 0.  Synchronises to read
@@ -306,6 +331,12 @@ typedef enum {
  * launches[SPG_KERNEL_COUNT]; either may be NULL. */
 spg_status spg_profile_begin(spg_problem* P, int32_t kernel_class, int32_t capacity);
 spg_status spg_profile_end(spg_problem* P, double* total_ms, int32_t* launches);
+
+/* Failure injection, for tests of the error paths (failure detection): the problem lets
+ * n more checked HIP calls succeed, then reports the next one as failed (after issuing it,
+ * as a device error found late would), which makes the problem return SPG_E_DEVICE from
+ * then on.  n = -1 turns injection off.  Host only; other problems are not affected. */
+spg_status spg_debug_fail_after(spg_problem* P, int32_t n);
 
 /* Static message for a status code; per-problem message of the last error. */
 const char* spg_status_string(spg_status s);

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <vector>
 
@@ -21,10 +22,11 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kStatBlocks = 1024;           // grid of the input-check / reweight kernels
-constexpr int kPartials = 65536;            // fp64 partials in the workspace
+constexpr int kPartials = 262144;           // fp64 partials in the workspace
 constexpr int kPartA = 0;                   // z-pass objective partials (<= 8192 blocks)
 constexpr int kPartB = 8192;                // kx = 0 / nx/2 plane partials (<= 257 blocks)
-constexpr int kPartC = 16384;               // stencil check partials (6 x <= 8192)
+constexpr int kPartC = 16384;               // stencil partials: check 6 x <= 8192, monitor 3 x <= 65536
+constexpr int kHistCap = 4096;              // monitored objectives kept (a ring)
 constexpr uint64_t kStateMagic = 0x5350475354415431ull;  // "SPGSTAT1"
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -36,7 +38,8 @@ bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1))
 bool axis_ok(int n) { return pow2_in(n, 4, 512) || n == 160 || n == 192; }
 
 struct Layout {
-  size_t xhi[3], xlo[3], u, v, S, rbuf, xprev, ws, w0p, wnyq, cs, c0p, cnyq, tw_m, tw_n, tw_y, tw_z, part, res, total;
+  size_t xhi[3], xlo[3], u, v, S, rbuf, xprev, ws, w0p, wnyq, cs, c0p, cnyq, tw_m, tw_n, tw_y, tw_z, part, res, hist,
+      total;
 };
 
 Layout make_layout(const spg_params& p) {
@@ -70,6 +73,7 @@ Layout make_layout(const spg_params& p) {
   L.tw_z = take((size_t)p.nz * 8);
   L.part = take((size_t)kPartials * 8);
   L.res = take(64 * 8);
+  L.hist = take((size_t)kHistCap * 8);
   L.total = off;
   return L;
 }
@@ -84,7 +88,9 @@ const char* check_params(const spg_params* p, spg_status* st) {
   if (!std::isfinite(p->eps) || p->eps <= 0) return "eps must be finite and > 0";
   if (!std::isfinite(p->gamma) || p->gamma < 0) return "gamma must be finite and >= 0";
   if (p->accel != 0 && p->accel != 1) return "accel must be 0 or 1";
-  if (p->flags & ~(SPG_FLAG_COMPENSATED | SPG_FLAG_BF16_STORAGE)) return "unknown flag bits";
+  if (p->flags & ~(SPG_FLAG_COMPENSATED | SPG_FLAG_BF16_STORAGE | SPG_FLAG_MONITOR)) return "unknown flag bits";
+  if (p->obj_every < 0 || ((p->flags & SPG_FLAG_MONITOR) && p->obj_every < 1))
+    return "obj_every must be >= 0, and >= 1 with SPG_FLAG_MONITOR";
   if ((p->flags & SPG_FLAG_COMPENSATED) && (p->flags & SPG_FLAG_BF16_STORAGE))
     return "SPG_FLAG_COMPENSATED and SPG_FLAG_BF16_STORAGE are exclusive";
   *st = SPG_OK;
@@ -132,6 +138,8 @@ struct spg_problem {
   bool data_set = false;
   bool primed = false;
   bool sticky = false;
+  bool dev_ready = false;   // twiddle tables uploaded and x_0 = 0 written
+  int32_t fail_after = -1;  // failure injection: checked HIP calls to let pass, -1 = off
   bool unif_u = true, unif_v = true;
   double maxwt = 0, vmax = 1, C0 = 0, L = 0, lr = 0, dn2 = 12;
   double rms_unreg = 0, mean_w = 0;  // parameter scales of the current data
@@ -139,6 +147,11 @@ struct spg_problem {
   int64_t iters_done = 0;
   int32_t round = 1;
   int32_t j = 1;         // index of the next iteration within the round (1-based)
+  // objective monitor: F_eps(y_j) of every iteration with j % mon_every == 0, into the
+  // device ring hist (slot = entry % kHistCap) with the iteration numbers on the host
+  int32_t mon_every = 0;
+  int64_t hist_n = 0;
+  std::vector<int64_t> hist_iter;
   double t = 1.0;        // FISTA t_j
   double m_cur = 0.0;    // momentum m_j of y_j
   char err[512] = {0};
@@ -185,15 +198,48 @@ spg_status fail_device(spg_problem* P, hipError_t e, const char* what) {
   return SPG_E_DEVICE;
 }
 
+// An injected failure (spg_debug_fail_after) reports the call as failed after issuing it,
+// as a device error found late would.
+hipError_t injected(spg_problem* P, hipError_t e) {
+  if (P->fail_after >= 0 && e == hipSuccess && P->fail_after-- == 0) return hipErrorLaunchFailure;
+  return e;
+}
+
 #define SPG_CK(P, expr)                                         \
   do {                                                          \
-    hipError_t e_ = (expr);                                     \
+    hipError_t e_ = injected((P), (expr));                      \
     if (e_ != hipSuccess) return fail_device((P), e_, #expr);   \
   } while (0)
+
+void restart(spg_problem* P);
+
+// Device state of a new problem, on its first call that enqueues work: the twiddle tables
+// exp(-2 pi i m / n), computed in fp64 and rounded once, and x_0 = 0.
+spg_status device_init(spg_problem* P) {
+  const spg_params* p = &P->prm;
+  const int lens[4] = {p->nx / 2, p->nx, p->ny, p->nz};
+  const size_t offs[4] = {P->lay.tw_m, P->lay.tw_n, P->lay.tw_y, P->lay.tw_z};
+  std::vector<float2> tab;
+  for (int t = 0; t < 4; ++t) {
+    const int n = lens[t];
+    tab.resize(n);
+    for (int m = 0; m < n; ++m) {
+      const double ang = -2.0 * M_PI * (double)m / (double)n;
+      tab[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    SPG_CK(P, hipMemcpyAsync(P->ws + offs[t], tab.data(), n * sizeof(float2), hipMemcpyHostToDevice, P->stream));
+    SPG_CK(P, hipStreamSynchronize(P->stream));
+  }
+  SPG_CK(P, launch_set_map(P->d, nullptr, P->xhi(P->cur), P->xlo(P->cur), P->stream));
+  restart(P);
+  P->dev_ready = true;
+  return SPG_OK;
+}
 
 spg_status usable(spg_problem* P) {
   if (!P) return SPG_E_INVAL;
   if (P->sticky) return SPG_E_DEVICE;
+  if (!P->dev_ready) return device_init(P);
   return SPG_OK;
 }
 
@@ -361,31 +407,16 @@ spg_status spg_create(const spg_params* p, void* d_workspace, size_t bytes, void
   P->store = P->comp ? ST_COMP : ((p->flags & SPG_FLAG_BF16_STORAGE) ? ST_BF16 : ST_PLAIN);
   P->dn2 = dnorm2_of(p->nx, p->ny, p->nz);
   P->fused = prox_fft_supported(P->d);
-
-  // Twiddle tables exp(-2 pi i m / n), computed in fp64 and rounded once.
-  const int lens[4] = {p->nx / 2, p->nx, p->ny, p->nz};
-  const size_t offs[4] = {lay.tw_m, lay.tw_n, lay.tw_y, lay.tw_z};
-  std::vector<float2> tab;
-  for (int t = 0; t < 4; ++t) {
-    const int n = lens[t];
-    tab.resize(n);
-    for (int m = 0; m < n; ++m) {
-      const double ang = -2.0 * M_PI * (double)m / (double)n;
-      tab[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-    }
-    hipError_t e = hipMemcpyAsync(P->ws + offs[t], tab.data(), n * sizeof(float2), hipMemcpyHostToDevice, P->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(P->stream);
-    if (e != hipSuccess) {
-      delete P;
-      return SPG_E_DEVICE;
-    }
-  }
-  if (launch_set_map(P->d, nullptr, P->xhi(P->cur), P->xlo(P->cur), P->stream) != hipSuccess) {
-    delete P;
-    return SPG_E_DEVICE;
-  }
+  P->mon_every = (p->flags & SPG_FLAG_MONITOR) ? p->obj_every : 0;
+  P->hist_iter.assign(kHistCap, 0);
   restart(P);
   *out = P;
+  return SPG_OK;
+}
+
+spg_status spg_debug_fail_after(spg_problem* P, int32_t n) {
+  if (!P || n < -1) return SPG_E_INVAL;
+  P->fail_after = n;
   return SPG_OK;
 }
 
@@ -508,21 +539,43 @@ static spg_status iterate_once(spg_problem* P, float* capture_g) {
       P->primed = true;
     }
     const bool fuse = P->fused && !capture_g;
-    if ((s = gradient_pipeline(P, false, nullptr, nullptr, P->rbuf(), P->bf(), !fuse))) return s;
+    // the objective monitor: F_eps(y_j) from partials of the z pass, the kx = 0 / nx/2 plane
+    // and the stencil kernel of this iteration
+    const bool mon = P->mon_every > 0 && !capture_g && P->j % P->mon_every == 0;
+    int nA = 0, nB = 0, nC = 0;
+    if ((s = gradient_pipeline(P, mon, &nA, &nB, P->rbuf(), P->bf(), !fuse))) return s;
     if (capture_g)
       SPG_CK(P, hipMemcpyAsync(capture_g, P->rbuf(), (size_t)d.nvox * 4, hipMemcpyDeviceToDevice, P->stream));
     const double t_next = P->prm.accel ? 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * P->t * P->t)) : 1.0;
     const double m_next = P->prm.accel ? (P->t - 1.0) / t_next : 0.0;
     const int nxt = 3 - P->cur - P->old;
     ProxArgs a = prox_args(P, nxt, P->m_cur, m_next);
+    if (mon) {
+      // 3 partials per block in region C (<= 3 x 65536; the slab depth does not change results)
+      a.partials = P->part() + kPartC;
+      if (fuse) {
+        nC = prox_fft_num_blocks(d, a.zc);
+      } else {
+        while (prox_num_blocks(d, a.zc) > 65536) a.zc *= 2;
+        nC = prox_num_blocks(d, a.zc);
+      }
+    }
     prof_begin(P, SPG_KERNEL_PROX_TV);
     if (fuse) {
       SPG_CK(P, launch_prox_fft(d, a, P->S(), P->at<float2>(P->lay.tw_m), P->at<float2>(P->lay.tw_n), P->store,
-                                P->stream));
+                                P->stream, mon));
     } else {
-      SPG_CK(P, launch_prox_tv(d, a, P->store, false, P->stream));
+      SPG_CK(P, launch_prox_tv(d, a, P->store, false, P->stream, mon));
     }
     prof_end(P, SPG_KERNEL_PROX_TV);
+    if (mon) {
+      const int slot = (int)(P->hist_n % kHistCap);
+      SPG_CK(P, launch_obj_finish(P->part() + kPartA, nA, P->part() + kPartB, nB, P->part() + kPartC, nC, P->C0,
+                                  P->prm.lambda, P->prm.mu, P->prm.gamma, P->at<double>(P->lay.hist) + slot,
+                                  P->stream));
+      P->hist_iter[slot] = P->iters_done + 1;
+      ++P->hist_n;
+    }
     if (!fuse && (s = r2c(P, P->rbuf(), P->bf()))) return s;
     P->old = P->cur;
     P->cur = nxt;
@@ -549,6 +602,35 @@ spg_status spg_run(spg_problem* P, int32_t K, spg_stats* stats) {
     stats->iter_in_round = P->j - 1;
     stats->lr = P->lr;
     stats->L = P->L;
+    stats->obj_smoothed = std::numeric_limits<double>::quiet_NaN();
+    stats->obj_iter = 0;
+    if (P->mon_every > 0 && P->hist_n > 0) {
+      const int slot = (int)((P->hist_n - 1) % kHistCap);
+      double v;
+      if ((s = read_results_to(P, P->at<double>(P->lay.hist) + slot, &v, 1))) return s;
+      stats->obj_smoothed = v;
+      stats->obj_iter = P->hist_iter[slot];
+      if (!std::isfinite(v)) return set_err(P, SPG_E_DIVERGED, "the monitored objective is not finite");
+    }
+  }
+  return SPG_OK;
+}
+
+spg_status spg_objective_history(spg_problem* P, double* h_values, int64_t* h_iters, int32_t cap, int32_t* n_out) {
+  spg_status s = usable(P);
+  if (s) return s;
+  if (!n_out || cap < 0 || (cap > 0 && !h_values && !h_iters))
+    return set_err(P, SPG_E_INVAL, "n_out must be given; cap >= 0 with an output array");
+  const int64_t avail = P->hist_n < kHistCap ? P->hist_n : kHistCap;
+  const int n = (int)(avail < cap ? avail : cap);
+  *n_out = n;
+  if (n == 0) return SPG_OK;
+  std::vector<double> ring(kHistCap);
+  if ((s = read_results_to(P, P->at<double>(P->lay.hist), ring.data(), kHistCap))) return s;
+  for (int i = 0; i < n; ++i) {  // the n most recent entries, oldest first
+    const int slot = (int)((P->hist_n - n + i) % kHistCap);
+    if (h_values) h_values[i] = ring[slot];
+    if (h_iters) h_iters[i] = P->hist_iter[slot];
   }
   return SPG_OK;
 }
@@ -882,6 +964,7 @@ struct IterSig {
   bool prior_set, primed, unif_u, unif_v, fused;
   double lr, t, m_cur;
   int32_t j;
+  int64_t hist_n;  // a graph with monitored iterations writes fixed history slots
   static IterSig of(const spg_problem* P) {
     IterSig g;
     g.prm = P->prm;
@@ -900,13 +983,15 @@ struct IterSig {
     g.t = P->t;
     g.m_cur = P->m_cur;
     g.j = P->j;
+    g.hist_n = P->hist_n;
     return g;
   }
   bool operator==(const IterSig& o) const {
     const spg_params& a = prm;
     const spg_params& b = o.prm;
     return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.lambda == b.lambda && a.mu == b.mu && a.eps == b.eps &&
-           a.gamma == b.gamma && a.accel == b.accel && a.flags == b.flags && store == o.store && cur == o.cur &&
+           a.gamma == b.gamma && a.accel == b.accel && a.flags == b.flags && a.obj_every == b.obj_every &&
+           hist_n == o.hist_n && store == o.store && cur == o.cur &&
            old == o.old && nt_y == o.nt_y && nt_z == o.nt_z && zc == o.zc && prior_set == o.prior_set &&
            primed == o.primed && unif_u == o.unif_u && unif_v == o.unif_v && fused == o.fused && lr == o.lr &&
            t == o.t && m_cur == o.m_cur && j == o.j;

@@ -62,8 +62,11 @@ int prox_num_blocks(const Dims& d, int zc);
 // x-spectrum of y_{k+1} back into S.  Grids with nx in {64, 128, 256, 512} and ny a
 // multiple of 4 (the kernel's tile height).
 bool prox_fft_supported(const Dims& d);
+int prox_fft_num_blocks(const Dims& d, int zc);
+// mon: also the per-block partials of the objective's penalty terms at y_k (3 x nblocks
+// into a.partials)
 hipError_t launch_prox_fft(const Dims& d, const ProxArgs& a, float2* S, const float2* tw_m, const float2* tw_n,
-                           int store, hipStream_t st);
+                           int store, hipStream_t st, bool mon = false);
 
 // persist: the fused z modes run persistent blocks (false: one block per tile, for
 // problems that share the GPU with concurrent work)
@@ -78,7 +81,8 @@ hipError_t launch_r2c_x(const Dims& d, const void* rin, bool rin_bf16, float2* S
                         const float2* tw_n, hipStream_t st);
 hipError_t launch_c2r_x(const Dims& d, const float2* S, void* rout, bool rout_bf16, const float2* tw_m,
                         const float2* tw_n, hipStream_t st);
-hipError_t launch_prox_tv(const Dims& d, const ProxArgs& a, int store, bool check, hipStream_t st);
+hipError_t launch_prox_tv(const Dims& d, const ProxArgs& a, int store, bool check, hipStream_t st,
+                          bool mon = false);
 
 hipError_t launch_prime(const Dims& d, void* rbuf, const float* xk_hi, const uint16_t* xk_lo,
                         const float* xo_hi, const uint16_t* xo_lo, double m, int read_old,
@@ -102,6 +106,9 @@ hipError_t launch_reweight(const Dims& d, const float* hi, const uint16_t* lo, v
 hipError_t launch_f32_to_bf16(const float* src, uint16_t* dst, long long n, hipStream_t st);
 hipError_t launch_bf16_to_f32(const uint16_t* src, float* dst, long long n, hipStream_t st);
 hipError_t launch_fill(float* dst, long long n, float value, hipStream_t st);
+// out = c0 + sum pa[na] + sum pb[nb] + lam sum pc[0:nc] + mu sum pc[nc:2nc] + gamma sum pc[2nc:3nc]
+hipError_t launch_obj_finish(const double* pa, int na, const double* pb, int nb, const double* pc, int nc, double c0,
+                             double lam, double mu, double gamma, double* out, hipStream_t st);
 hipError_t launch_reduce(const double* partials, int n, int nq, const int* ops, double* out, hipStream_t st);
 hipError_t launch_adj_prox(const Dims& d, const float* xn, const float* abar, const float* gdat, const float* u,
                            float lr, float* zbar, float* rbar, double* partials, int nblocks, hipStream_t st);

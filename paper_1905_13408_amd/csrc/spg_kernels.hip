@@ -891,6 +891,13 @@ __device__ __forceinline__ float inv_norm(const ProxArgs& a, float n2) {
   return n2 > a.eps * a.eps ? rsqrtf(n2) : 1.0f / a.eps;
 }
 
+// phi_eps(|Dy|) of eq 14 in fp64 from |Dy|^2: t^2 / (2 eps) below eps, t - eps/2 above.
+__device__ __forceinline__ double huber64(float n2, float eps) {
+  const double nd = sqrt((double)n2);
+  const double e = eps;
+  return nd < e ? nd * nd / (2.0 * e) : nd - 0.5 * e;
+}
+
 template <bool COMP>
 __device__ __forceinline__ void fetch_raw(const ProxArgs& a, long long i, RawX& r) {
   r.xh = a.xk_hi[i];
@@ -919,8 +926,12 @@ __device__ __forceinline__ void eval_raw(const ProxArgs& a, const RawX& r, doubl
   }
 }
 
-template <int ST, bool CHECK>
+// MON (with CHECK false): the iteration as usual, and per-block fp64 partials of the
+// penalty terms of the objective at y_k: sum u |y|, sum v phi_eps(|Dy|), sum (y - x_prev)^2
+// (3 groups of gridDim.x in a.partials).
+template <int ST, bool CHECK, bool MON = false>
 __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
+  static_assert(!(CHECK && MON), "check mode evaluates the objective itself");
   constexpr bool COMP = ST == ST_COMP;
   constexpr bool BF = ST == ST_BF16;
   constexpr int TX = PT_TX, TY = PT_TY;
@@ -1045,6 +1056,9 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
           acc_hub += (double)vv[t] * hub;
           acc_tv0 += (double)vv[t] * nd;
         }
+      } else if constexpr (MON) {
+        if (count && lx < TX && ly < TY && (x0 + lx) < nx && (y0 + ly) < ny)
+          acc_hub += (double)vv[t] * huber64(n2, a.eps);
       }
     }
   };
@@ -1112,6 +1126,10 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
             acc_x2 += y * y;
             acc_gam += dprior * dprior;
           } else {
+            if constexpr (MON) {
+              acc_l1 += (double)uu * fabs(y);
+              acc_gam += dprior * dprior;
+            }
             const float hi = (float)xn;
             const uint16_t lo = f32_to_bf16((float)(xn - (double)hi));
             a.xn_hi[i] = hi;
@@ -1133,6 +1151,10 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
             acc_x2 += (double)y * y;
             acc_gam += (double)dprior * dprior;
           } else {
+            if constexpr (MON) {
+              acc_l1 += (double)uu * fabs((double)y);
+              acc_gam += (double)dprior * dprior;
+            }
             a.xn_hi[i] = xn;
             const float xk = (float)own_xk[h];
             st_real<BF>(a.rbuf, i, xn + (float)a.m_next * (xn - xk));
@@ -1163,6 +1185,15 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
     if (tid == 0) a.partials[4 * nb + blk] = r;
     r = block_reduce<RED_OP_SUM>(acc_gam, s_red);
     if (tid == 0) a.partials[5 * nb + blk] = r;
+  } else if constexpr (MON) {
+    const int nb = gridDim.x;
+    double r;
+    r = block_reduce<RED_OP_SUM>(acc_l1, s_red);
+    if (tid == 0) a.partials[blk] = r;
+    r = block_reduce<RED_OP_SUM>(acc_hub, s_red);
+    if (tid == 0) a.partials[nb + blk] = r;
+    r = block_reduce<RED_OP_SUM>(acc_gam, s_red);
+    if (tid == 0) a.partials[2 * nb + blk] = r;
   }
 }
 
@@ -1198,8 +1229,11 @@ struct PfT {  // threads per row of the M-point complex transforms
 
 // PRIOR: the gamma term's previous map is given (else it is 0).  NT: x_{k+1} and the
 // spectrum rows go out by streaming stores (maps whose spectrum outgrows the last-level
-// cache; smaller maps are read back by the next pass while still cached).
-template <int NX, int ST, bool PRIOR, bool NT>
+// cache; smaller maps are read back by the next pass while still cached).  MON: also the
+// per-block fp64 partials of the penalty terms of the objective at y_k (eq 31 with eq 14):
+// sum u |y|, sum v phi_eps(|Dy|) and sum (y - x_prev)^2, into a.partials (3 groups of
+// gridDim.x).
+template <int NX, int ST, bool PRIOR, bool NT, bool MON = false>
 __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restrict__ S,
                                                      const float2* __restrict__ twm,
                                                      const float2* __restrict__ twn, int nty) {
@@ -1327,27 +1361,32 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
     eval(halo, yv, xv);
     Y[hly + 1][x] = (float)yv;
   };
-  // sc = v / max(eps, |Dy|) at row ly of plane zz, column x (backward differences)
-  auto sc_at = [&](int zz, int ly, float vv) {
+  // |Dy|^2 at row ly of plane zz, column x (backward differences)
+  auto n2_at = [&](int zz, int ly) {
     const float(*Y)[NX] = sY[slot3(zz)];
     const float(*Yp)[NX] = sY[slot3(zz - 1)];
     const float yc = Y[ly + 1][x];
     const float dxv = yc - Y[ly + 1][xm];
     const float dyv = yc - Y[ly][x];
     const float dzv = yc - Yp[ly + 1][x];
-    const float n2 = dxv * dxv + dyv * dyv + dzv * dzv;
-    const float inv = inv_norm(a, n2);
-    return vv * inv;
+    return dxv * dxv + dyv * dyv + dzv * dzv;
   };
-  // writes the ring slot of plane zz and returns the thread's own values in sco
+  // objective partials (MON): penalty terms of the voxels this thread owns on this slab
+  double acc_l1 = 0.0, acc_hub = 0.0, acc_gam = 0.0;
+  // sc = v / max(eps, |Dy|): writes the ring slot of plane zz and returns the thread's own
+  // values in sco
   auto compute_sc = [&](int zz, const float* vv, float* sco) {
     float(*SC)[NX] = sSC[zz & 1];
 #pragma unroll
     for (int h = 0; h < NO; ++h) {
-      sco[h] = sc_at(zz, r + 2 * h, vv[h]);
+      const float n2 = n2_at(zz, r + 2 * h);
+      sco[h] = vv[h] * inv_norm(a, n2);
       SC[r + 2 * h][x] = sco[h];
+      if constexpr (MON) {
+        if (zz < z1) acc_hub += (double)vv[h] * huber64(n2, a.eps);
+      }
     }
-    if (r == 1) SC[TY][x] = sc_at(zz, TY, vv[NO]);
+    if (r == 1) SC[TY][x] = vv[NO] * inv_norm(a, n2_at(zz, TY));
   };
   // One transform phase.  Forward half (fr < NR): the y_{k+1} rows of the batch at plane
   // zf (planes < zf_end) from sG into S.  Inverse half: the spectrum rows in `sa` of the
@@ -1510,6 +1549,10 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
             const double t = a.lr * a.lam * (double)uu;
             const double az = fabs(zv) - t;
             const double xn = az > 0.0 ? copysign(az, zv) : 0.0;
+            if constexpr (MON) {
+              acc_l1 += (double)uu * fabs(y);
+              acc_gam += dprior * dprior;
+            }
             const float hi = (float)xn;
             const uint16_t lo = f32_to_bf16((float)(xn - (double)hi));
             st_nt<NT>(xnh, own_off[h] * 4u, hi);
@@ -1523,6 +1566,10 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
             const float t = (float)a.lr * (float)a.lam * uu;
             const float az = fabsf(zv) - t;
             const float xn = az > 0.f ? copysignf(az, zv) : 0.f;
+            if constexpr (MON) {
+              acc_l1 += (double)uu * fabs((double)y);
+              acc_gam += (double)dprior * dprior;
+            }
             st_nt<NT>(xnh, own_off[h] * 4u, xn);
             const float xk = (float)own_xk[h];
             ynext = xn + (float)a.m_next * (xn - xk);
@@ -1542,6 +1589,16 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
     transform_phase(zb, zb_end, zb + KB, sa);
     fetch_spec(zb + 2 * KB, sa);
     __syncthreads();  // the exchange rows are rewritten by the next phase
+  }
+  if constexpr (MON) {
+    __shared__ double s_red[16];
+    const int nb = gridDim.x;
+    double rr = block_reduce<RED_OP_SUM>(acc_l1, s_red);
+    if (tid == 0) a.partials[blockIdx.x] = rr;
+    rr = block_reduce<RED_OP_SUM>(acc_hub, s_red);
+    if (tid == 0) a.partials[nb + blockIdx.x] = rr;
+    rr = block_reduce<RED_OP_SUM>(acc_gam, s_red);
+    if (tid == 0) a.partials[2 * nb + blockIdx.x] = rr;
   }
 }
 
@@ -2039,6 +2096,28 @@ __global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ parti
   }
 }
 
+// The monitored objective F_eps(y_k) (eq 31 with eq 14) from fixed-order sums of the
+// partials: C0 + data partials of the z pass (pa) and of the kx = 0 / nx/2 plane (pb), plus
+// lam sum u|y| + mu sum v phi_eps + gamma sum (y - x_prev)^2 from the stencil kernel (pc:
+// three groups of nc).  One block; writes *out.
+__global__ void __launch_bounds__(256) k_obj_finish(const double* __restrict__ pa, int na,
+                                                    const double* __restrict__ pb, int nb,
+                                                    const double* __restrict__ pc, int nc, double c0, double lam,
+                                                    double mu, double gamma, double* __restrict__ out) {
+  __shared__ double s_red[8];
+  auto sum = [&](const double* p, int n) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += p[i];
+    return block_reduce<RED_OP_SUM>(acc, s_red);
+  };
+  const double A = sum(pa, na);
+  const double B = sum(pb, nb);
+  const double L1 = sum(pc, nc);
+  const double H = sum(pc + nc, nc);
+  const double G = sum(pc + 2 * (long long)nc, nc);
+  if (threadIdx.x == 0) *out = c0 + A + B + lam * L1 + mu * H + gamma * G;
+}
+
 // ---------------------------------------------------------------- launchers
 
 #define SPG_DISPATCH_L(Lv, CALL)        \
@@ -2211,13 +2290,14 @@ int prox_num_blocks(const Dims& d, int zc) {
   return ntx * nty * ntz;
 }
 
-hipError_t launch_prox_tv(const Dims& d, const ProxArgs& a, int store, bool check, hipStream_t st) {
+hipError_t launch_prox_tv(const Dims& d, const ProxArgs& a, int store, bool check, hipStream_t st, bool mon) {
   const int ntx = (d.nx + PT_TX - 1) / PT_TX;
   const int nty = (d.ny + PT_TY - 1) / PT_TY;
-  if (a.zc < 1) return hipErrorInvalidValue;
+  if (a.zc < 1 || (check && mon)) return hipErrorInvalidValue;
   const dim3 grid(prox_num_blocks(d, a.zc)), block(256);
 #define SPG_PROX(ST_) \
   do { if (check) k_prox_tv<ST_, true><<<grid, block, 0, st>>>(a, ntx, nty); \
+       else if (mon) k_prox_tv<ST_, false, true><<<grid, block, 0, st>>>(a, ntx, nty); \
        else k_prox_tv<ST_, false><<<grid, block, 0, st>>>(a, ntx, nty); } while (0)
   switch (store) {
     case ST_PLAIN: SPG_PROX(ST_PLAIN); break;
@@ -2240,8 +2320,10 @@ bool prox_fft_supported(const Dims& d) {
   return (d.nx == 64 || d.nx == 128 || d.nx == 256 || d.nx == 512) && d.ny >= PF_TY && d.ny % PF_TY == 0;
 }
 
+int prox_fft_num_blocks(const Dims& d, int zc) { return (d.ny / PF_TY) * ((d.nz + zc - 1) / zc); }
+
 hipError_t launch_prox_fft(const Dims& d, const ProxArgs& a, float2* S, const float2* tw_m, const float2* tw_n,
-                           int store, hipStream_t st) {
+                           int store, hipStream_t st, bool mon) {
   if (!prox_fft_supported(d) || a.zc < 1 || store < ST_PLAIN || store > ST_BF16) return hipErrorInvalidValue;
   const int nty = d.ny / PF_TY;
   const long long nblk = (long long)nty * ((d.nz + a.zc - 1) / a.zc);
@@ -2252,7 +2334,9 @@ hipError_t launch_prox_fft(const Dims& d, const ProxArgs& a, float2* S, const fl
   // still cached (measured on the batch of 128^3-256^3 maps).
   const bool stream = (double)d.nvox * 4.0 >= 256.0 * 1024 * 1024;
 #define SPG_PF2(NX_, ST_)                                                                          \
-  if (a.xprev) k_prox_fft<NX_, ST_, true, false><<<grid, block, 0, st>>>(a, S, tw_m, tw_n, nty);      \
+  if (mon && a.xprev) k_prox_fft<NX_, ST_, true, false, true><<<grid, block, 0, st>>>(a, S, tw_m, tw_n, nty); \
+  else if (mon) k_prox_fft<NX_, ST_, false, false, true><<<grid, block, 0, st>>>(a, S, tw_m, tw_n, nty); \
+  else if (a.xprev) k_prox_fft<NX_, ST_, true, false><<<grid, block, 0, st>>>(a, S, tw_m, tw_n, nty); \
   else if (stream) k_prox_fft<NX_, ST_, false, true><<<grid, block, 0, st>>>(a, S, tw_m, tw_n, nty);     \
   else k_prox_fft<NX_, ST_, false, false><<<grid, block, 0, st>>>(a, S, tw_m, tw_n, nty);
 #define SPG_PF(NX_)                                   \
@@ -2337,6 +2421,12 @@ hipError_t launch_log_terms(const Dims& d, const float* hi, const uint16_t* lo, 
                             double* partials, int nblocks, hipStream_t st) {
   if (comp) k_reweight<true, false, true><<<nblocks, 256, 0, st>>>(d, hi, lo, nullptr, nullptr, eps1, eps2, partials);
   else k_reweight<false, false, true><<<nblocks, 256, 0, st>>>(d, hi, lo, nullptr, nullptr, eps1, eps2, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_obj_finish(const double* pa, int na, const double* pb, int nb, const double* pc, int nc, double c0,
+                             double lam, double mu, double gamma, double* out, hipStream_t st) {
+  k_obj_finish<<<1, 256, 0, st>>>(pa, na, pb, nb, pc, nc, c0, lam, mu, gamma, out);
   return hipGetLastError();
 }
 

@@ -14,25 +14,29 @@ from dataclasses import dataclass
 from typing import Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libspg.so")
+# SPG_LIB_PATH selects another build of the same library (the host-sanitizer build of the
+# CPU tests); the default is the in-tree libspg.so
+LIB_PATH = os.environ.get("SPG_LIB_PATH") or os.path.join(HERE, "libspg.so")
 
 SPG_OK = 0
 STATUS_NAMES = {0: "SPG_OK", -1: "SPG_E_INVAL", -2: "SPG_E_NOMEM", -3: "SPG_E_DEVICE", -4: "SPG_E_STATE",
                 -5: "SPG_E_NONFINITE", -6: "SPG_E_DIVERGED", -7: "SPG_E_UNSUPPORTED"}
 FLAG_COMPENSATED = 1
 FLAG_BF16_STORAGE = 2
+FLAG_MONITOR = 4
 
 KERNELS = ["fft_y_fwd", "fft_z_weight", "dc_nyquist", "fft_y_inv", "c2r_x", "prox_tv", "r2c_x"]
 
 
 class Params(Structure):
     _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("lambda_", c_double), ("mu", c_double),
-                ("eps", c_double), ("gamma", c_double), ("accel", c_int32), ("flags", c_int32)]
+                ("eps", c_double), ("gamma", c_double), ("accel", c_int32), ("flags", c_int32),
+                ("obj_every", c_int32)]
 
 
 class Stats(Structure):
     _fields_ = [("iters_done", c_int64), ("round", c_int32), ("iter_in_round", c_int32), ("lr", c_double),
-                ("L", c_double)]
+                ("L", c_double), ("obj_smoothed", c_double), ("obj_iter", c_int64)]
 
 
 class SPGError(RuntimeError):
@@ -57,12 +61,14 @@ def lib() -> ctypes.CDLL:
         "spg_workspace_size": [POINTER(Params), POINTER(c_size_t)],
         "spg_create": [POINTER(Params), P, c_size_t, P, POINTER(P)],
         "spg_destroy": [P],
+        "spg_debug_fail_after": [P, c_int32],
         "spg_set_data": [P, P, P],
         "spg_set_penalty_weights": [P, P, P],
         "spg_set_params": [P, c_double, c_double],
         "spg_set_map": [P, P],
         "spg_set_prior": [P, c_double, P],
         "spg_run": [P, c_int32, POINTER(Stats)],
+        "spg_objective_history": [P, POINTER(c_double), POINTER(c_int64), c_int32, POINTER(c_int32)],
         "spg_reweight": [P, c_double, c_double],
         "spg_get_map": [P, P],
         "spg_get_penalty_weights": [P, P, P],
@@ -106,12 +112,16 @@ def lib() -> ctypes.CDLL:
 STORAGE = {"compensated": FLAG_COMPENSATED, "fp32": 0, "bf16": FLAG_BF16_STORAGE}
 
 
-def make_params(shape, lam, mu, eps, accel=True, compensated=True, gamma=0.0, storage=None) -> Params:
-    """storage: 'compensated' (default), 'fp32' or 'bf16'; `compensated=False` means 'fp32'."""
+def make_params(shape, lam, mu, eps, accel=True, compensated=True, gamma=0.0, storage=None,
+                monitor_every=0) -> Params:
+    """storage: 'compensated' (default), 'fp32' or 'bf16'; `compensated=False` means 'fp32'.
+    monitor_every > 0 turns on the objective monitor (SPG_FLAG_MONITOR, obj_every)."""
     nz, ny, nx = (int(s) for s in shape)
     if storage is None:
         storage = "compensated" if compensated else "fp32"
-    return Params(nx, ny, nz, float(lam), float(mu), float(eps), float(gamma), 1 if accel else 0, STORAGE[storage])
+    flags = STORAGE[storage] | (FLAG_MONITOR if monitor_every else 0)
+    return Params(nx, ny, nz, float(lam), float(mu), float(eps), float(gamma), 1 if accel else 0, flags,
+                  int(monitor_every))
 
 
 def workspace_size(shape, lam=0.01, mu=0.05, eps=1e-3, accel=True, compensated=True, gamma=0.0, storage=None) -> int:
@@ -130,6 +140,8 @@ class RunStats:
     iter_in_round: int
     lr: float
     L: float
+    obj_smoothed: float = float("nan")
+    obj_iter: int = 0
 
 
 def _ptr(t) -> c_void_p:
@@ -144,7 +156,7 @@ class SPGSolver:
     """
 
     def __init__(self, shape, lam, mu, eps, accel=True, compensated=True, device="cuda", stream=None, storage=None,
-                 gamma=0.0):
+                 gamma=0.0, monitor_every=0):
         import torch
 
         self.torch = torch
@@ -153,7 +165,7 @@ class SPGSolver:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.storage = storage if storage is not None else ("compensated" if compensated else "fp32")
         self._L = lib()
-        p = make_params(self.shape, lam, mu, eps, accel, compensated, gamma, self.storage)
+        p = make_params(self.shape, lam, mu, eps, accel, compensated, gamma, self.storage, monitor_every)
         n = c_size_t(0)
         self._check(self._L.spg_workspace_size(byref(p), byref(n)), None)
         self.ws_bytes = int(n.value)
@@ -217,7 +229,19 @@ class SPGSolver:
     def run(self, K: int) -> RunStats:
         s = Stats()
         self._check(self._L.spg_run(self._h, int(K), byref(s)))
-        return RunStats(s.iters_done, s.round, s.iter_in_round, s.lr, s.L)
+        return RunStats(s.iters_done, s.round, s.iter_in_round, s.lr, s.L, s.obj_smoothed, s.obj_iter)
+
+    def debug_fail_after(self, n: int):
+        """Failure injection: report the (n+1)-th next checked HIP call as failed (-1: off)."""
+        self._check(self._L.spg_debug_fail_after(self._h, int(n)))
+
+    def objective_history(self, cap: int = 4096):
+        """(iterations k, F_eps(y_k)) of the objective monitor, oldest first."""
+        vals = (c_double * cap)()
+        its = (c_int64 * cap)()
+        n = c_int32(0)
+        self._check(self._L.spg_objective_history(self._h, vals, its, int(cap), byref(n)))
+        return [int(its[i]) for i in range(n.value)], [float(vals[i]) for i in range(n.value)]
 
     def reweight(self, eps1, eps2):
         self._check(self._L.spg_reweight(self._h, float(eps1), float(eps2)))

@@ -48,7 +48,8 @@ def test_workspace_size_model():
     b = _ws((nz, ny, nx))
     # 3 fp32 + 3 bf16 iterate slots, u, v, spectrum, map buffer, prior map, folded weights and data
     core = 3 * 4 * n + 3 * 2 * n + 2 * 4 * n + 4 * n + 4 * n + 4 * n + 2 * n + 4 * n
-    assert core <= b <= core + 2 * 1024 * 1024
+    # plus fixed tables: twiddles, 2 MiB of fp64 reduction partials, the monitor's history
+    assert core <= b <= core + 3 * 1024 * 1024
     assert _ws((nz, ny, nx), compensated=False) == b - 3 * 2 * n
     # bf16 storage: u, v and the map buffer at 2 bytes
     assert _ws((nz, ny, nx), storage="bf16") == b - 3 * 2 * n - 3 * 2 * n
@@ -59,8 +60,22 @@ def test_storage_flags_are_exclusive(L):
     p.flags = spg.FLAG_COMPENSATED | spg.FLAG_BF16_STORAGE
     n = ctypes.c_size_t()
     assert L.spg_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1
-    p.flags = 4
+    p.flags = 8
     assert L.spg_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1
+
+
+def test_monitor_flag_needs_a_period(L):
+    p = spg.make_params((8, 8, 8), 0.01, 0.05, 1e-3)
+    n = ctypes.c_size_t()
+    p.flags = spg.FLAG_COMPENSATED | spg.FLAG_MONITOR
+    p.obj_every = 0
+    assert L.spg_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1
+    p.obj_every = -3
+    assert L.spg_workspace_size(ctypes.byref(p), ctypes.byref(n)) == -1
+    p.obj_every = 10
+    assert L.spg_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0
+    # the monitor's history lives in the fixed tables: no per-voxel bytes
+    assert n.value == _ws((8, 8, 8))
 
 
 def test_gamma_is_accepted():
@@ -121,3 +136,36 @@ def test_fsc_argument_validation(L):
     assert L.spg_fsc_workspace_size(8, 8, 8, 5, ctypes.byref(n)) == 0 and n.value > 2 * 8 * 8 * 4 * 8
     out = (ctypes.c_double * 5)()
     assert L.spg_fsc(8, 8, 8, None, None, 5, None, 0, None, out) == -1
+
+
+def _device_visible() -> bool:
+    import torch
+
+    return torch.cuda.device_count() > 0
+
+
+@pytest.mark.skipif(_device_visible(), reason="runs where no GPU is visible: its workspace pointer is never "
+                                              "dereferenced only because every HIP call fails there")
+def test_device_failure_is_sticky(L):
+    """A problem whose first device call fails (here: no device) answers SPG_E_DEVICE from then
+    on, keeps the first error message, still answers host-only queries, and is destroyed
+    cleanly."""
+    p = spg.make_params((8, 8, 8), 0.01, 0.05, 1e-3)
+    need = _ws((8, 8, 8))
+    fake = ctypes.c_void_p(1 << 20)
+    h = ctypes.c_void_p()
+    assert L.spg_create(ctypes.byref(p), fake, need, None, ctypes.byref(h)) == 0 and h.value
+    assert L.spg_set_data(h, fake, fake) == -3
+    msg = L.spg_last_error(h)
+    assert msg.startswith(b"HIP error in "), msg
+    for st in (L.spg_run(h, 1, None), L.spg_set_map(h, None), L.spg_reweight(h, 0.1, 0.1),
+               L.spg_get_map(h, fake), L.spg_final_check(h, None, None, None), L.spg_set_fusion(h, 0)):
+        assert st == -3
+    assert L.spg_last_error(h) == msg
+    # host-only calls still answer: no data was set
+    d = ctypes.c_double()
+    assert L.spg_param_scales(h, ctypes.byref(d), None) == -4
+    on = ctypes.c_int32()
+    assert L.spg_get_fusion(h, ctypes.byref(on)) == 0
+    assert L.spg_debug_fail_after(h, -2) == -1 and L.spg_debug_fail_after(h, 3) == 0
+    assert L.spg_destroy(h) == 0
