@@ -76,8 +76,9 @@ def summarize(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, 
         if cls == "prox_tv":
             # iteration launches only: the fused kernel where it ran, else the stencil kernel
             # outside its check mode (another instance)
-            fv = [v for k, lst in fa.items() if k.startswith(FUSED) for v in lst]
-            wv = [v for k, lst in wa.items() if k.startswith(FUSED) for v in lst]
+            # (the objective-monitor instance, a trailing "true>", is not an iteration launch)
+            fv = [v for k, lst in fa.items() if k.startswith(FUSED) and not k.endswith("true>") for v in lst]
+            wv = [v for k, lst in wa.items() if k.startswith(FUSED) and not k.endswith("true>") for v in lst]
             if not fv:
                 fv = [v for k, lst in fa.items() if k.startswith(prefix) and k.endswith("false>") for v in lst]
                 wv = [v for k, lst in wa.items() if k.startswith(prefix) and k.endswith("false>") for v in lst]

@@ -23,11 +23,13 @@ def test_summarize_scales_by_the_copy_and_picks_iteration_kernels(tmp_path):
     _csv(tmp_path / "cw.csv", [("__amd_rocclr_copyBuffer(...)", "WRITE_SIZE", copy_bytes / 1024)])
     fetch = [("void spg::k_fft_cols<512, 0>(...)", "FETCH_SIZE", 100.0),
              ("void spg::k_fft_cols<512, 0>(...)", "FETCH_SIZE", 300.0),
-             ("void spg::k_prox_fft<512, 1, false, true>(...)", "FETCH_SIZE", 1000.0),
+             ("void spg::k_prox_fft<512, 1, false, true, false>(...)", "FETCH_SIZE", 1000.0),
+             ("void spg::k_prox_fft<512, 1, false, false, true>(...)", "FETCH_SIZE", 5.0),  # monitor: not counted
              ("void spg::k_prox_tv<1, true>(...)", "FETCH_SIZE", 7.0)]     # check launch: not counted
     write = [("void spg::k_fft_cols<512, 0>(...)", "WRITE_SIZE", 50.0),
              ("void spg::k_fft_cols<512, 0>(...)", "WRITE_SIZE", 50.0),
-             ("void spg::k_prox_fft<512, 1, false, true>(...)", "WRITE_SIZE", 400.0),
+             ("void spg::k_prox_fft<512, 1, false, true, false>(...)", "WRITE_SIZE", 400.0),
+             ("void spg::k_prox_fft<512, 1, false, false, true>(...)", "WRITE_SIZE", 3.0),
              ("void spg::k_prox_tv<1, true>(...)", "WRITE_SIZE", 9.0)]
     _csv(tmp_path / "f.csv", fetch)
     _csv(tmp_path / "w.csv", write)
