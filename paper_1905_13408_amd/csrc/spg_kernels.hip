@@ -387,6 +387,84 @@ __device__ __forceinline__ void fft_reg(float2 (&a)[reg_e(L, TT)], float* re, fl
   reg_stages<L, TT, 0, INV, RegPlan<L, TT>::ns, SWZ>(a, re, im, ps, q, twl, act);
 }
 
+// fft_reg<256, false, 32, true> (the 512-point real rows of a 512-wide map) with its LDS
+// positions written out: stages radix 8, 8, 4 over the points q + 32 i of thread q < 32.
+// The swizzled position of each stage's element reduces, because q < 32, to a per-thread
+// base XOR a constant (bytes):
+//   stage 0 writes 8q + (r ^ (q >> 2))            -> (32q | 4(q >> 2)) ^ 4r
+//   stage 1 reads  (q + 32r) ^ r = q ^ 33r        -> 4q ^ 132r
+//   stage 1 writes 64a + (q & 7) + 8(r ^ a), a = q >> 3 -> (256a | 32a | 4(q & 7)) ^ 32r
+//   stage 2 reads  (q + 32b + 64r) ^ 8r           -> 4q ^ (128b + 288r)
+// so each access costs one XOR and one add of the row base instead of the generic index
+// arithmetic.  Same twiddles, products and butterflies as the generic stages, so the results
+// are bitwise those of fft_reg.
+__device__ __forceinline__ void row_fft256(float2 (&a)[8], float* re, float* im, int q,
+                                           const float2* __restrict__ twl, bool act) {
+  char* rb = reinterpret_cast<char*>(re);
+  char* ib = reinterpret_cast<char*>(im);
+  auto st = [&](unsigned off, float2 v) {
+    *reinterpret_cast<float*>(rb + off) = v.x;
+    *reinterpret_cast<float*>(ib + off) = v.y;
+  };
+  auto ld = [&](unsigned off) {
+    return make_float2(*reinterpret_cast<const float*>(rb + off), *reinterpret_cast<const float*>(ib + off));
+  };
+  const unsigned uq = (unsigned)q;
+  const unsigned q4 = uq * 4u;
+  // stage 0 (radix 8, span 1): the thread's own points, no twiddles
+  {
+    float2 v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) v[r] = a[r];
+    dft8<false>(v);
+    if (act) {
+      const unsigned b0 = (uq * 32u) | (uq & 28u);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) st(b0 ^ (4u * r), v[r]);
+    }
+    __syncthreads();
+  }
+  // stage 1 (radix 8, span 8)
+  {
+    float2 v[8];
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) v[r] = ld(q4 ^ (132u * r));
+    }
+    __syncthreads();
+    if (act) {
+      const int k = q & 7;
+#pragma unroll
+      for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], twl[r * k * 4]);
+      dft8<false>(v);
+      const unsigned ua = uq >> 3;
+      const unsigned b1 = (ua * 256u) | (ua * 32u) | ((uq & 7u) * 4u);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) st(b1 ^ (32u * r), v[r]);
+    }
+    __syncthreads();
+  }
+  // stage 2 (radix 4, span 64, last): two butterflies b, results back to a[b + 2r]
+  {
+    float2 v[2][4];
+    if (act) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[b][r] = ld(q4 ^ (128u * b + 288u * r));
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int j = q + 32 * b;
+#pragma unroll
+        for (int r = 1; r < 4; ++r) v[b][r] = cmul(v[b][r], twl[r * j]);
+        dft4<false>(v[b]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[b + 2 * r] = v[b][r];
+      }
+    }
+  }
+}
+
 // Threads per column of the column passes: more threads for the long axes keep the
 // per-thread state of the fused z pass (data, folded weight and data term) small.  At
 // 512 points, 64 threads of 8 values each hold it near 110 VGPRs, so a 16-column tile
@@ -1431,7 +1509,8 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
       }
     }
     __syncthreads();
-    fft_reg<M, false, FT, true>(v, fre, fim, 1, fq, s_tw, act);
+    if constexpr (M == 256 && FT == 32) row_fft256(v, fre, fim, fq, s_tw, act);
+    else fft_reg<M, false, FT, true>(v, fre, fim, 1, fq, s_tw, act);
     if (act && !fwd) {  // z = conj(FFT(conj Z)): interleaved real samples of the row
 #pragma unroll
       for (int i = 0; i < FE; ++i)
