@@ -304,8 +304,8 @@ spg_status spg_backproject(int32_t nx, int32_t ny, int32_t nz, int32_t n_img, in
  * signed frequency k (for a cubic grid the rounded |k|), s in [0, nshells), 1 <= nshells
  * <= 1024; a shell without power in either map gives 0.  h_fsc receives nshells host
  * doubles.  The workspace (device, 256-byte aligned, spg_fsc_workspace_size bytes) is the
- * caller's; the call synchronises the stream.  Shell sums use fp64 atomics in LDS, so
- * results can differ between runs in the last bits. */
+ * caller's; the call synchronises the stream.  Shell sums are fp64 in a fixed order, so
+ * results are bitwise reproducible. */
 spg_status spg_fsc_workspace_size(int32_t nx, int32_t ny, int32_t nz, int32_t nshells, size_t* bytes);
 spg_status spg_fsc(int32_t nx, int32_t ny, int32_t nz, const float* d_map1, const float* d_map2, int32_t nshells,
                    void* d_workspace, size_t bytes, void* hip_stream, double* h_fsc);

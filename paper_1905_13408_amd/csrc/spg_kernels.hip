@@ -1907,8 +1907,11 @@ __global__ void __launch_bounds__(256) k_reweight(Dims d, const float* __restric
 // Shell sums of eq 30 over the packed half spectra of two real maps: Re F conj G, |F|^2,
 // |G|^2 per shell, with multiplicity 2 for 0 < kx < nx/2.  The packed slot 0 is split
 // into its kx = 0 and kx = nx/2 planes with the partner at (-ky, -kz).  Shell of signed
-// frequency k: floor(min(n) sqrt(sum_a (k_a / n_a)^2) + 1/2).  Per-block histograms in
-// LDS (fp64 atomics), written as block partials.
+// frequency k: floor(min(n) sqrt(sum_a (k_a / n_a)^2) + 1/2).  Deterministic: every wave
+// keeps its own histogram in LDS; the lanes' terms of one shell are summed by a fixed
+// butterfly over the wave and added by lane 0, so no two adds to one LDS word race; the
+// block partial sums the wave histograms in wave order, and k_fsc_final the blocks in
+// block order.
 __device__ __forceinline__ int fsc_shell(int kz, int ky, int kx, const Dims& d) {
   const int nmin = min(d.nx, min(d.ny, d.nz));
   const int sz = kz < d.nz / 2 ? kz : kz - d.nz;
@@ -1918,43 +1921,85 @@ __device__ __forceinline__ int fsc_shell(int kz, int ky, int kx, const Dims& d) 
   return (int)floor(sqrt(fz * fz + fy * fy + fx * fx) + 0.5);
 }
 
-__global__ void __launch_bounds__(256) k_fsc_shells(Dims d, const float2* __restrict__ S1,
-                                                    const float2* __restrict__ S2, int nshells,
-                                                    double* __restrict__ partials) {
-  extern __shared__ double sh[];  // 3 * nshells
-  for (int i = threadIdx.x; i < 3 * nshells; i += blockDim.x) sh[i] = 0.0;
+constexpr int FSC_THREADS = 128;  // two waves per block: 2 x 3 x 1024 fp64 histogram words at most
+
+__global__ void __launch_bounds__(FSC_THREADS) k_fsc_shells(Dims d, const float2* __restrict__ S1,
+                                                            const float2* __restrict__ S2, int nshells,
+                                                            double* __restrict__ partials) {
+  extern __shared__ double sh[];  // per wave: 3 * nshells
+  constexpr int NW = FSC_THREADS / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* hw = sh + (size_t)wave * 3 * nshells;
+  for (int i = threadIdx.x; i < NW * 3 * nshells; i += blockDim.x) sh[i] = 0.0;
   __syncthreads();
-  auto acc = [&](int shell, double w, float2 f, float2 g) {
-    if (shell < nshells) {
-      atomicAdd(&sh[shell], w * ((double)f.x * g.x + (double)f.y * g.y));
-      atomicAdd(&sh[nshells + shell], w * ((double)f.x * f.x + (double)f.y * f.y));
-      atomicAdd(&sh[2 * nshells + shell], w * ((double)g.x * g.x + (double)g.y * g.y));
+  // all 64 lanes call this together; a lane with shell < 0 contributes nothing
+  auto wave_add = [&](int shell, double a, double b, double c) {
+    int mine = shell < nshells ? shell : -1;
+    for (;;) {
+      const unsigned long long pend = __ballot(mine >= 0);
+      if (pend == 0ull) break;
+      const int s = __shfl(mine, __ffsll((long long)pend) - 1);
+      const bool take = mine == s;
+      double x = take ? a : 0.0, y = take ? b : 0.0, z = take ? c : 0.0;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        x += __shfl_xor(x, off);
+        y += __shfl_xor(y, off);
+        z += __shfl_xor(z, off);
+      }
+      if (lane == 0) {
+        hw[s] += x;
+        hw[nshells + s] += y;
+        hw[2 * nshells + s] += z;
+      }
+      if (take) mine = -1;
     }
   };
   const int P = d.P;
   const long long nh = (long long)d.nz * d.ny * P;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nh; t += (long long)gridDim.x * blockDim.x) {
-    const int kx = (int)(t % P);
-    const long long r = t / P;
-    const int ky = (int)(r % d.ny);
-    const int kz = (int)(r / d.ny);
-    const float2 f = S1[t], g = S2[t];
-    if (kx > 0) {
-      acc(fsc_shell(kz, ky, kx, d), 2.0, f, g);
-    } else {
-      const long long tp = ((long long)((d.nz - kz) % d.nz) * d.ny + ((d.ny - ky) % d.ny)) * P;
-      const float2 fp = S1[tp], gp = S2[tp];
-      const float2 f0 = make_float2(0.5f * (f.x + fp.x), 0.5f * (f.y - fp.y));
-      const float2 fn = make_float2(0.5f * (f.y + fp.y), -0.5f * (f.x - fp.x));
-      const float2 g0 = make_float2(0.5f * (g.x + gp.x), 0.5f * (g.y - gp.y));
-      const float2 gn = make_float2(0.5f * (g.y + gp.y), -0.5f * (g.x - gp.x));
-      acc(fsc_shell(kz, ky, 0, d), 1.0, f0, g0);
-      acc(fsc_shell(kz, ky, d.nx / 2, d), 1.0, fn, gn);
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  // block-uniform trip count: lanes past the end take part with no terms
+  for (long long t0 = (long long)blockIdx.x * blockDim.x; t0 < nh; t0 += stride) {
+    const long long t = t0 + threadIdx.x;
+    int s1 = -1, s2 = -1;
+    double a1 = 0.0, b1 = 0.0, c1 = 0.0, a2 = 0.0, b2 = 0.0, c2 = 0.0;
+    if (t < nh) {
+      const int kx = (int)(t % P);
+      const long long r = t / P;
+      const int ky = (int)(r % d.ny);
+      const int kz = (int)(r / d.ny);
+      const float2 f = S1[t], g = S2[t];
+      auto terms = [](double w, float2 f_, float2 g_, double& a, double& b, double& c) {
+        a = w * ((double)f_.x * g_.x + (double)f_.y * g_.y);
+        b = w * ((double)f_.x * f_.x + (double)f_.y * f_.y);
+        c = w * ((double)g_.x * g_.x + (double)g_.y * g_.y);
+      };
+      if (kx > 0) {
+        s1 = fsc_shell(kz, ky, kx, d);
+        terms(2.0, f, g, a1, b1, c1);
+      } else {
+        const long long tp = ((long long)((d.nz - kz) % d.nz) * d.ny + ((d.ny - ky) % d.ny)) * P;
+        const float2 fp = S1[tp], gp = S2[tp];
+        const float2 f0 = make_float2(0.5f * (f.x + fp.x), 0.5f * (f.y - fp.y));
+        const float2 fn = make_float2(0.5f * (f.y + fp.y), -0.5f * (f.x - fp.x));
+        const float2 g0 = make_float2(0.5f * (g.x + gp.x), 0.5f * (g.y - gp.y));
+        const float2 gn = make_float2(0.5f * (g.y + gp.y), -0.5f * (g.x - gp.x));
+        s1 = fsc_shell(kz, ky, 0, d);
+        terms(1.0, f0, g0, a1, b1, c1);
+        s2 = fsc_shell(kz, ky, d.nx / 2, d);
+        terms(1.0, fn, gn, a2, b2, c2);
+      }
     }
+    wave_add(s1, a1, b1, c1);
+    wave_add(s2, a2, b2, c2);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 3 * nshells; i += blockDim.x)
-    partials[(long long)blockIdx.x * 3 * nshells + i] = sh[i];
+  for (int i = threadIdx.x; i < 3 * nshells; i += blockDim.x) {
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) v += sh[(size_t)w * 3 * nshells + i];
+    partials[(long long)blockIdx.x * 3 * nshells + i] = v;
+  }
 }
 
 // Fixed-order sum of the block histograms: out[q * nshells + s], q = 0..2.
@@ -2519,7 +2564,8 @@ hipError_t launch_reduce(const double* partials, int n, int nq, const int* ops, 
 
 hipError_t launch_fsc_shells(const Dims& d, const float2* S1, const float2* S2, int nshells, double* partials,
                              int nblocks, double* out, hipStream_t st) {
-  k_fsc_shells<<<nblocks, 256, 3 * nshells * sizeof(double), st>>>(d, S1, S2, nshells, partials);
+  k_fsc_shells<<<nblocks, FSC_THREADS, (FSC_THREADS / 64) * 3 * nshells * sizeof(double), st>>>(d, S1, S2, nshells,
+                                                                                                 partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_fsc_final<<<(3 * nshells + 255) / 256, 256, 0, st>>>(partials, nblocks, nshells, out);

@@ -416,6 +416,9 @@ def test_fsc_matches_oracle(shape):
     ref = FR.fsc(a.astype(np.float64), b.astype(np.float64), nsh)
     print("fsc max abs diff", float(np.max(np.abs(got - ref))), flush=True)
     assert np.max(np.abs(got - ref)) < 1e-5
+    # fixed-order shell sums: a second call gives the same bits
+    again = spg.fsc(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), nsh)
+    assert np.array_equal(got, again)
     same = spg.fsc(torch.from_numpy(a).cuda(), torch.from_numpy(a).cuda(), nsh)
     assert np.max(np.abs(same - 1.0)) < 1e-6
 
