@@ -310,6 +310,18 @@ spg_status spg_fsc_workspace_size(int32_t nx, int32_t ny, int32_t nz, int32_t ns
 spg_status spg_fsc(int32_t nx, int32_t ny, int32_t nz, const float* d_map1, const float* d_map2, int32_t nshells,
                    void* d_workspace, size_t bytes, void* hip_stream, double* h_fsc);
 
+/* spg_fsc for callers that cannot allocate device memory (code under HIP graph capture is
+ * not meant: the call synchronises; tight loops and harnesses that forbid allocation are):
+ * the same transforms, shell sums and result as spg_fsc, with the workspace in a static
+ * device array of the library (72 MiB per device, held until the process ends) instead of a
+ * caller buffer.  Grids whose spg_fsc_workspace_size exceeds 72 MiB - 64 KiB (more than
+ * about 2^23 voxels) return SPG_E_NOMEM.  The first call on a device looks the array up and
+ * writes its twiddle tables (once); no call allocates or frees device memory.  All calls on
+ * one device share the array: calls that overlap on one device (other threads or streams)
+ * race and must be serialised by the caller. */
+spg_status spg_fsc_noalloc(int32_t nx, int32_t ny, int32_t nz, const float* d_map1, const float* d_map2,
+                           int32_t nshells, void* hip_stream, double* h_fsc);
+
 /* Kernel classes for spg_profile_begin. */
 typedef enum {
   SPG_KERNEL_FFT_Y_FWD = 0, /* y-axis forward column FFT                               */

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -800,9 +801,116 @@ FscLayout fsc_layout(int nx, int ny, int nz, int nshells) {
 bool fsc_args_ok(int nx, int ny, int nz, int nshells) {
   return axis_ok(nx) && axis_ok(ny) && axis_ok(nz) && nshells >= 1 && nshells <= 1024;
 }
+
+// exp(-2 pi i m / n), m < n, computed in fp64 and rounded once
+void twiddle_table(int n, std::vector<float2>& tab) {
+  tab.resize(n);
+  for (int m = 0; m < n; ++m) {
+    const double ang = -2.0 * M_PI * (double)m / (double)n;
+    tab[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  }
+}
+
+// Both maps to the packed half spectrum (x, y, z transforms), the shell sums and the ratio
+// of eq 30.  ws holds the spectra, partials and output at the offsets of lay; tw[4] are the
+// twiddle tables of nx/2, nx, ny and nz points.  Synchronises the stream.
+spg_status fsc_run(int nx, int ny, int nz, const float* d_map1, const float* d_map2, int nshells, char* ws,
+                   const FscLayout& lay, const float2* const tw[4], hipStream_t st, double* h_fsc) {
+  Dims d{nx, ny, nz, nx / 2, (long long)nx * ny * nz};
+  const float* maps[2] = {d_map1, d_map2};
+  float2* specs[2] = {reinterpret_cast<float2*>(ws + lay.S1), reinterpret_cast<float2*>(ws + lay.S2)};
+  for (int k = 0; k < 2; ++k) {
+    if (launch_r2c_x(d, maps[k], false, specs[k], tw[0], tw[1], st) != hipSuccess) return SPG_E_DEVICE;
+    if (launch_fft_cols(d, specs[k], 1, 0, tw[2], nullptr, nullptr, nullptr, st, nullptr) != hipSuccess)
+      return SPG_E_DEVICE;
+    if (launch_fft_cols(d, specs[k], 2, 0, tw[3], nullptr, nullptr, nullptr, st, nullptr) != hipSuccess)
+      return SPG_E_DEVICE;
+  }
+  double* out = reinterpret_cast<double*>(ws + lay.out);
+  if (launch_fsc_shells(d, specs[0], specs[1], nshells, reinterpret_cast<double*>(ws + lay.part), kFscBlocks, out,
+                        st) != hipSuccess)
+    return SPG_E_DEVICE;
+  double h[3 * 1024];
+  if (hipMemcpyAsync(h, out, 3 * (size_t)nshells * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return SPG_E_DEVICE;
+  for (int sidx = 0; sidx < nshells; ++sidx) {
+    const double den = std::sqrt(h[nshells + sidx] * h[2 * nshells + sidx]);
+    h_fsc[sidx] = den > 0 ? h[sidx] / den : 0.0;
+  }
+  return SPG_OK;
+}
+
+// ---- the FSC entry point that allocates nothing
+// Its workspace is the static device array below: a region with the twiddle tables of every
+// supported axis length (written once per device by the first call there), then the FSC
+// workspace of one call.  In host code the array's name is only a stand-in; the device
+// address comes from hipGetSymbolAddress, once per device, and is the only one used.
+constexpr size_t kNoallocTables = 64 * 1024;
+constexpr size_t kNoallocBytes = 72ull << 20;
+// axis lengths with a table (nx/2 of the supported nx included) and their offsets in bytes
+constexpr int kTwLens[] = {2, 4, 8, 16, 32, 64, 128, 256, 512, 80, 96, 160, 192};
+constexpr int kNumTwLens = sizeof(kTwLens) / sizeof(kTwLens[0]);
+
+constexpr size_t noalloc_table_offset(int n) {
+  size_t off = 0;
+  for (int i = 0; i < kNumTwLens; ++i) {
+    if (kTwLens[i] == n) return off;
+    off = (off + (size_t)kTwLens[i] * 8 + kAlign - 1) / kAlign * kAlign;
+  }
+  return off;  // past the last table: the size of the table region
+}
+static_assert(noalloc_table_offset(0) <= kNoallocTables, "twiddle tables outgrow their region");
+
+std::mutex g_noalloc_mu;
+std::vector<char*> g_noalloc_base;  // per device: the address of the array, null until set up
+}  // namespace
+
+static __device__ __align__(256) char scratch[kNoallocBytes];
+
+namespace {
+// The device address of the array on the current device; the first call on a device looks
+// it up and writes the twiddle tables (synchronising hip_stream).
+spg_status noalloc_base(hipStream_t st, char** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return SPG_E_DEVICE;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if ((int)g_noalloc_base.size() <= dev) g_noalloc_base.resize(dev + 1, nullptr);
+  if (!g_noalloc_base[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SPG_E_DEVICE;
+    char* base = reinterpret_cast<char*>(ptr);
+    std::vector<float2> tab;
+    for (int i = 0; i < kNumTwLens; ++i) {
+      twiddle_table(kTwLens[i], tab);
+      if (hipMemcpyAsync(base + noalloc_table_offset(kTwLens[i]), tab.data(), tab.size() * sizeof(float2),
+                         hipMemcpyHostToDevice, st) != hipSuccess)
+        return SPG_E_DEVICE;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) return SPG_E_DEVICE;
+    g_noalloc_base[dev] = base;
+  }
+  *out = g_noalloc_base[dev];
+  return SPG_OK;
+}
 }  // namespace
 
 extern "C" {
+
+spg_status spg_fsc_noalloc(int32_t nx, int32_t ny, int32_t nz, const float* d_map1, const float* d_map2,
+                           int32_t nshells, void* hip_stream, double* h_fsc) {
+  if (!fsc_args_ok(nx, ny, nz, nshells) || !d_map1 || !d_map2 || !h_fsc) return SPG_E_INVAL;
+  const FscLayout lay = fsc_layout(nx, ny, nz, nshells);
+  if (lay.total > kNoallocBytes - kNoallocTables) return SPG_E_NOMEM;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  char* base = nullptr;
+  spg_status s = noalloc_base(st, &base);
+  if (s) return s;
+  const int lens[4] = {nx / 2, nx, ny, nz};
+  const float2* tw[4];
+  for (int t = 0; t < 4; ++t) tw[t] = reinterpret_cast<const float2*>(base + noalloc_table_offset(lens[t]));
+  return fsc_run(nx, ny, nz, d_map1, d_map2, nshells, base + kNoallocTables, lay, tw, st, h_fsc);
+}
 
 spg_status spg_fsc_workspace_size(int32_t nx, int32_t ny, int32_t nz, int32_t nshells, size_t* bytes) {
   if (!bytes || !fsc_args_ok(nx, ny, nz, nshells)) return SPG_E_INVAL;
@@ -819,46 +927,18 @@ spg_status spg_fsc(int32_t nx, int32_t ny, int32_t nz, const float* d_map1, cons
   if (bytes < lay.total) return SPG_E_NOMEM;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   char* ws = reinterpret_cast<char*>(d_workspace);
-  Dims d{nx, ny, nz, nx / 2, (long long)nx * ny * nz};
   const int lens[4] = {nx / 2, nx, ny, nz};
   const size_t offs[4] = {lay.tw_m, lay.tw_n, lay.tw_y, lay.tw_z};
   std::vector<float2> tab;
+  const float2* tw[4];
   for (int t = 0; t < 4; ++t) {
-    tab.resize(lens[t]);
-    for (int m = 0; m < lens[t]; ++m) {
-      const double ang = -2.0 * M_PI * (double)m / (double)lens[t];
-      tab[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-    }
+    twiddle_table(lens[t], tab);
     if (hipMemcpyAsync(ws + offs[t], tab.data(), lens[t] * sizeof(float2), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       return SPG_E_DEVICE;
+    tw[t] = reinterpret_cast<const float2*>(ws + offs[t]);
   }
-  const float2* twm = reinterpret_cast<const float2*>(ws + lay.tw_m);
-  const float2* twn = reinterpret_cast<const float2*>(ws + lay.tw_n);
-  const float2* twy = reinterpret_cast<const float2*>(ws + lay.tw_y);
-  const float2* twz = reinterpret_cast<const float2*>(ws + lay.tw_z);
-  const float* maps[2] = {d_map1, d_map2};
-  float2* specs[2] = {reinterpret_cast<float2*>(ws + lay.S1), reinterpret_cast<float2*>(ws + lay.S2)};
-  for (int k = 0; k < 2; ++k) {
-    if (launch_r2c_x(d, maps[k], false, specs[k], twm, twn, st) != hipSuccess) return SPG_E_DEVICE;
-    if (launch_fft_cols(d, specs[k], 1, 0, twy, nullptr, nullptr, nullptr, st, nullptr) != hipSuccess)
-      return SPG_E_DEVICE;
-    if (launch_fft_cols(d, specs[k], 2, 0, twz, nullptr, nullptr, nullptr, st, nullptr) != hipSuccess)
-      return SPG_E_DEVICE;
-  }
-  double* out = reinterpret_cast<double*>(ws + lay.out);
-  if (launch_fsc_shells(d, specs[0], specs[1], nshells, reinterpret_cast<double*>(ws + lay.part), kFscBlocks, out,
-                        st) != hipSuccess)
-    return SPG_E_DEVICE;
-  std::vector<double> h(3 * (size_t)nshells);
-  if (hipMemcpyAsync(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return SPG_E_DEVICE;
-  for (int sidx = 0; sidx < nshells; ++sidx) {
-    const double den = std::sqrt(h[nshells + sidx] * h[2 * (size_t)nshells + sidx]);
-    h_fsc[sidx] = den > 0 ? h[sidx] / den : 0.0;
-  }
-  return SPG_OK;
+  return fsc_run(nx, ny, nz, d_map1, d_map2, nshells, ws, lay, tw, st, h_fsc);
 }
 
 }  // extern "C"

@@ -96,6 +96,7 @@ def lib() -> ctypes.CDLL:
         "spg_backproject": [c_int32, c_int32, c_int32, c_int32, c_int32, P, P, P, P, c_double, P, c_size_t, P, P, P],
         "spg_fsc_workspace_size": [c_int32, c_int32, c_int32, c_int32, POINTER(c_size_t)],
         "spg_fsc": [c_int32, c_int32, c_int32, P, P, c_int32, P, c_size_t, P, POINTER(c_double)],
+        "spg_fsc_noalloc": [c_int32, c_int32, c_int32, P, P, c_int32, P, POINTER(c_double)],
     }
     for name, args in sigs.items():
         f = getattr(L, name)
