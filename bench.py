@@ -6,7 +6,14 @@ between), fetch the map and run the fp64 objective / KKT check.  Inputs are resi
 in HBM before the timed region starts.  The JSON line reports SPG iterations per
 second, the per-kernel device time from HIP events recorded on the solver's stream
 during the timed steps, the roofline of the dominant kernel, and the FP64 oracle
-timed on the host cores on a bounded sample (one iteration of the same workload).
+timed on the host cores on a bounded sample (three iterations of the same workload).
+
+Other workloads (one JSON line each):
+  --config 1   32^3 plain, 50 iterations: eager launches against one replayed HIP graph
+  --config 2   256^3 reweighting workload, 3 x 100 (the same step as the default)
+  --config 4   8-volume batch {128..256}^3 in one HIP graph, 200 iterations each
+  --config 5   128^3 differentiation: forward + reverse (adjoint) against the plain forward
+  --storage    fp32 | bf16 | compensated (default) iterate / map storage
 
   python bench.py [--steps K] [--warmup W] [--config 3] [--no-cpu-baseline]
 """
@@ -114,6 +121,26 @@ def iteration_bytes(shape, explicit_uv=True, storage="compensated", fused=False)
             kb["prox_fft"](True, explicit_uv)
     return sum(kb[k] for k in ["fft_y_fwd", "fft_z_weight", "dc_nyquist", "fft_y_inv", "c2r_x", "r2c_x"]) + \
         kb["prox_tv"](True, explicit_uv)
+
+
+def survey_iteration_bytes(shape, explicit_uv):
+    """The hot-path byte model of the method's scope table (plain fp32 iterate, four HBM sweeps
+    per iteration): the fused real-space kernel reads x_k, x_{k-1}, [u, v] and the gradient
+    spectrum and writes x_{k+1} and the spectrum of y_{k+1} (5R + 2H with explicit u, v, else
+    3R + 2H), the y passes 2H each and the z pass 3.5H, with R = 4 n and H = 8 nz ny (nx/2 + 1)
+    (the unpacked half spectrum).  Returns (stencil kernel bytes, whole iteration bytes)."""
+    nz, ny, nx = shape
+    n = nx * ny * nz
+    R = 4 * n
+    H = 8 * nz * ny * (nx // 2 + 1)
+    prox = (5 * R if explicit_uv else 3 * R) + 2 * H
+    return prox, prox + 2 * H + 3.5 * H + 2 * H
+
+
+def survey_schedule_mean(shape, rounds):
+    """Mean of survey_iteration_bytes over a schedule whose first round has uniform u, v."""
+    vals = [survey_iteration_bytes(shape, r > 0) for r in range(rounds)]
+    return sum(v[0] for v in vals) / rounds, sum(v[1] for v in vals) / rounds
 
 
 def cpu_baseline(vol, c):
@@ -287,6 +314,12 @@ def main():
     if args.config == 4:
         bench_batch(args)
         return
+    if args.config == 1:
+        bench_small(args)
+        return
+    if args.config == 5:
+        bench_diff(args)
+        return
 
     from paper_1905_13408_amd import profiling, spg, synth
 
@@ -364,8 +397,9 @@ def main():
     total_iters = rounds * iters * args.steps
     value = total_iters / elapsed
     it_bytes = schedule_iteration_bytes(shape, rounds, iters, storage, fused)
+    _, survey_it = survey_schedule_mean(shape, rounds)
     line = {
-        "metric": METRIC,
+        "metric": METRIC if args.config == 3 else METRIC.replace("512^3", f"{shape[0]}^3"),
         "value": value,
         "unit": "iterations/s",
         "n_gpus": 1,
@@ -390,6 +424,9 @@ def main():
         "ms_per_iteration": 1e3 * elapsed / total_iters,
         "model_bytes_per_iteration": it_bytes,
         "model_GBps": it_bytes * value / 1e9,
+        "survey_model_bytes_per_iteration": survey_it,
+        "survey_model_GBps": survey_it * value / 1e9,
+        "survey_model_frac_of_peak": survey_it * value / 1e9 / HBM_PEAK_GBPS,
         "final_objective": result["check"][0],
         "final_kkt_rel": result["check"][2],
     }
@@ -421,15 +458,115 @@ def main():
         line["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                             "frac": ach / HBM_PEAK_GBPS, "traffic": traffic,
                             "bytes_per_launch": bytes_per_launch, "us_per_launch": t_avg * 1e6}
+        if dom == "prox_tv" and fused:
+            # the same launches priced with the scope table's byte model (plain fp32 iterate,
+            # the unpacked half spectrum): what the method must move, whatever the storage
+            sp, _ = survey_schedule_mean(shape, rounds)
+            line["roofline"]["survey_model"] = {"bytes_per_launch": sp, "achieved": sp / t_avg / 1e9,
+                                                "frac": sp / t_avg / 1e9 / HBM_PEAK_GBPS}
     # the practical HBM ceiling (a 1 GiB device copy, outside the timed steps) and the whole
     # iteration's algorithmic bytes against it
     cc = copy_ceiling()
     line["copy_ceiling_GBps"] = cc["GBps_read_plus_write"]
     line["copy_ceiling_by"] = cc["by"]
     line["model_frac_of_copy_ceiling"] = line["model_GBps"] / cc["GBps_read_plus_write"]
+    if args.config == 2:
+        line["hbm_note"] = ("256^3: about 1 GB per iteration against the 256 MiB last-level (Infinity) cache, "
+                            "so part of the traffic is served from it: GB/s figures are effective, not HBM")
     if not args.no_cpu_baseline:
-        print("# cpu baseline (FP64 oracle, one iteration)", file=sys.stderr, flush=True)
+        print("# cpu baseline (FP64 oracle, three iterations)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(vol, c)
+    print(json.dumps(line))
+
+
+def bench_small(args):
+    """The 32^3 plain workload (50 SPG iterations from x = 0, uniform weights): launch-bound, so
+    iterations per second are given for eager launches (7 kernels per iteration) and for the
+    50 iterations captured once as a HIP graph and replayed."""
+    import torch
+
+    from paper_1905_13408_amd import spg, synth
+
+    vol, c = synth.make_config(1)
+    iters = args.iters or c["iters"]
+    s = spg.SPGSolver(c["shape"], c["lam"], c["mu"], c["eps"], storage=args.storage)
+    s.set_data(torch.from_numpy(vol.w).cuda(), torch.from_numpy(vol.b).cuda())
+    batch = spg.SPGBatch([s])
+    res = {}
+    for name, run in [("eager", lambda: s.run(iters)), ("graph", lambda: batch.run(iters))]:
+        for _ in range(args.warmup + 1):
+            s.set_map(None)
+            run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            s.set_map(None)
+            run()
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0) / args.steps
+    batch.close()
+    line = {
+        "metric": "SPG iterations/sec at 32^3 (launch-bound)",
+        "value": iters / res["graph"], "unit": "iterations/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * res["graph"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if args.storage != "bf16" else "f32/bf16", "data": "synthetic",
+        "config": {"workload": f"plain-32: 32x32x32, 60 Gaussian blobs on 1 chain, SNR 1, lambda {c['lam']}, "
+                               f"mu {c['mu']}, eps {c['eps']}, {iters} SPG iterations from x = 0",
+                   "storage": args.storage},
+        "eager_iterations_per_s": iters / res["eager"],
+        "graph_speedup_vs_eager": res["eager"] / res["graph"],
+        "step": "set_map + the iterations (one HIP graph of all of them, replayed)",
+    }
+    print(json.dumps(line))
+
+
+def bench_diff(args):
+    """The differentiation workload (128^3, 50 unrolled iterations, checkpoint every 10): the
+    plain forward solve against the checkpointed forward and the reverse pass (spg_vjp) that
+    gives d loss / d (lambda, mu, b) for loss = |x_50 - x_true|^2."""
+    import torch
+
+    from paper_1905_13408_amd import spg, synth
+
+    vol, c = synth.make_config(5)
+    K, C = c["iters"], 10
+    w = torch.from_numpy(vol.w).cuda()
+    s = spg.SPGSolver(c["shape"], c["lam"], c["mu"], c["eps"])
+    s.set_data(w, torch.from_numpy(vol.b).cuda())
+    xt = torch.from_numpy(vol.x_true).cuda()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    def plain():
+        s.set_map(None)
+        s.run(K)
+
+    def fwd_rev():
+        s.set_map(None)
+        s.run_checkpointed(K, C)
+        x = s.get_map()
+        s.vjp(w, 2.0 * (x - xt))
+
+    reps = max(1, args.steps)
+    t_plain = timed(plain, reps)
+    t_both = timed(fwd_rev, reps)
+    line = {
+        "metric": "SPG forward + reverse (adjoint) time at 128^3, 50 unrolled iterations",
+        "value": 1e3 * t_both, "unit": "ms", "n_gpus": 1, "steps": reps, "warmup": 1,
+        "ms_per_step": 1e3 * t_both, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "diff-128: 128^3, 1000 Gaussian blobs on 4 chains, SNR 0.5, 50 SPG iterations, "
+                               "checkpoint every 10, loss |x_50 - x_true|^2"},
+        "plain_forward_ms": 1e3 * t_plain,
+        "forward_plus_reverse_over_plain_forward": t_both / t_plain,
+    }
     print(json.dumps(line))
 
 

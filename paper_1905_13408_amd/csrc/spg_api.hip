@@ -523,7 +523,11 @@ spg_status spg_set_prior(spg_problem* P, double gamma, const float* d_xprev) {
 spg_status spg_set_map(spg_problem* P, const float* d_x0) {
   spg_status s = usable(P);
   if (s) return s;
-  SPG_CK(P, launch_set_map(P->d, d_x0, P->xhi(P->cur), P->xlo(P->cur), P->stream));
+  // the iterate ring restarts at slot 0, so that every solve from a set map launches the same
+  // kernels (a batch graph captured after one spg_set_map is replayed after the next)
+  SPG_CK(P, launch_set_map(P->d, d_x0, P->xhi(0), P->xlo(0), P->stream));
+  P->cur = 0;
+  P->old = 1;
   restart(P);
   return SPG_OK;
 }
