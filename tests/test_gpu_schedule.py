@@ -166,3 +166,12 @@ def test_schedule_512_bench_launch_shape():
     d = float(torch.linalg.vector_norm((xf - xs).double()) / torch.linalg.vector_norm(xs.double()))
     print(f"512^3 fused vs separate sweeps: rel L2 {d:.3e}", flush=True)
     assert d < 1e-6
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+def test_schedule_512_other_storage(storage):
+    """The 512^3 schedule of the previous test in the plain fp32 and bf16 storage modes, at
+    the same launch shape: their errors against the oracle per output, within the bf16 bar."""
+    announce(f"512^3 precision workload 10 + reweight + 10, storage={storage}")
+    rows, _ = _schedule_vs_fixture("precision512_10r10", storage, launch_shape=(16, 16, 256), fusion=True)
+    assert max(e for _, _, e, _ in rows) < BAR[storage]
