@@ -123,9 +123,9 @@ def iteration_bytes(shape, explicit_uv=True, storage="compensated", fused=False)
         kb["prox_tv"](True, explicit_uv)
 
 
-def survey_iteration_bytes(shape, explicit_uv):
-    """The hot-path byte model of the method's scope table (plain fp32 iterate, four HBM sweeps
-    per iteration): the fused real-space kernel reads x_k, x_{k-1}, [u, v] and the gradient
+def plain_iteration_bytes(shape, explicit_uv):
+    """A byte model of the path with a plain fp32 iterate and four HBM sweeps per iteration,
+    independent of this implementation's storage choices: the fused real-space kernel reads x_k, x_{k-1}, [u, v] and the gradient
     spectrum and writes x_{k+1} and the spectrum of y_{k+1} (5R + 2H with explicit u, v, else
     3R + 2H), the y passes 2H each and the z pass 3.5H, with R = 4 n and H = 8 nz ny (nx/2 + 1)
     (the unpacked half spectrum).  Returns (stencil kernel bytes, whole iteration bytes)."""
@@ -137,9 +137,9 @@ def survey_iteration_bytes(shape, explicit_uv):
     return prox, prox + 2 * H + 3.5 * H + 2 * H
 
 
-def survey_schedule_mean(shape, rounds):
-    """Mean of survey_iteration_bytes over a schedule whose first round has uniform u, v."""
-    vals = [survey_iteration_bytes(shape, r > 0) for r in range(rounds)]
+def plain_schedule_mean(shape, rounds):
+    """Mean of plain_iteration_bytes over a schedule whose first round has uniform u, v."""
+    vals = [plain_iteration_bytes(shape, r > 0) for r in range(rounds)]
     return sum(v[0] for v in vals) / rounds, sum(v[1] for v in vals) / rounds
 
 
@@ -397,7 +397,7 @@ def main():
     total_iters = rounds * iters * args.steps
     value = total_iters / elapsed
     it_bytes = schedule_iteration_bytes(shape, rounds, iters, storage, fused)
-    _, survey_it = survey_schedule_mean(shape, rounds)
+    _, plain_it = plain_schedule_mean(shape, rounds)
     line = {
         "metric": METRIC if args.config == 3 else METRIC.replace("512^3", f"{shape[0]}^3"),
         "value": value,
@@ -424,9 +424,9 @@ def main():
         "ms_per_iteration": 1e3 * elapsed / total_iters,
         "model_bytes_per_iteration": it_bytes,
         "model_GBps": it_bytes * value / 1e9,
-        "survey_model_bytes_per_iteration": survey_it,
-        "survey_model_GBps": survey_it * value / 1e9,
-        "survey_model_frac_of_peak": survey_it * value / 1e9 / HBM_PEAK_GBPS,
+        "plain_fp32_model_bytes_per_iteration": plain_it,
+        "plain_fp32_model_GBps": plain_it * value / 1e9,
+        "plain_fp32_model_frac_of_peak": plain_it * value / 1e9 / HBM_PEAK_GBPS,
         "final_objective": result["check"][0],
         "final_kkt_rel": result["check"][2],
     }
@@ -459,10 +459,10 @@ def main():
                             "frac": ach / HBM_PEAK_GBPS, "traffic": traffic,
                             "bytes_per_launch": bytes_per_launch, "us_per_launch": t_avg * 1e6}
         if dom == "prox_tv" and fused:
-            # the same launches priced with the scope table's byte model (plain fp32 iterate,
-            # the unpacked half spectrum): what the method must move, whatever the storage
-            sp, _ = survey_schedule_mean(shape, rounds)
-            line["roofline"]["survey_model"] = {"bytes_per_launch": sp, "achieved": sp / t_avg / 1e9,
+            # the same launches priced with the plain fp32 byte model (unpacked half spectrum):
+            # what the method must move, whatever the storage
+            sp, _ = plain_schedule_mean(shape, rounds)
+            line["roofline"]["plain_fp32_model"] = {"bytes_per_launch": sp, "achieved": sp / t_avg / 1e9,
                                                 "frac": sp / t_avg / 1e9 / HBM_PEAK_GBPS}
     # the practical HBM ceiling (a 1 GiB device copy, outside the timed steps) and the whole
     # iteration's algorithmic bytes against it
