@@ -398,60 +398,71 @@ __device__ __forceinline__ void fft_reg(float2 (&a)[reg_e(L, TT)], float* re, fl
 // so each access costs one XOR and one add of the row base instead of the generic index
 // arithmetic.  Same twiddles, products and butterflies as the generic stages, so the results
 // are bitwise those of fft_reg.
-__device__ __forceinline__ void row_fft256(float2 (&a)[8], float* re, float* im, int q,
-                                           const float2* __restrict__ twl, bool act) {
-  char* rb = reinterpret_cast<char*>(re);
-  char* ib = reinterpret_cast<char*>(im);
-  auto st = [&](unsigned off, float2 v) {
+// Orders the LDS accesses of one wavefront across this point.  A wavefront executes its LDS
+// instructions in order, so data exchanged among its own lanes needs no s_barrier; this only
+// keeps the compiler from moving accesses across.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The stages of row_fft256, for callers that interleave them with other work (the barriers
+// between them are the caller's): s0 transforms the thread's own points and writes them, s1r
+// reads the stage-1 inputs, s1w twiddles, transforms and writes them, s2 reads, twiddles and
+// transforms the last stage back into a[b + 2r].
+struct Row256 {
+  static __device__ __forceinline__ void st(char* rb, char* ib, unsigned off, float2 v) {
     *reinterpret_cast<float*>(rb + off) = v.x;
     *reinterpret_cast<float*>(ib + off) = v.y;
-  };
-  auto ld = [&](unsigned off) {
+  }
+  static __device__ __forceinline__ float2 ld(const char* rb, const char* ib, unsigned off) {
     return make_float2(*reinterpret_cast<const float*>(rb + off), *reinterpret_cast<const float*>(ib + off));
-  };
-  const unsigned uq = (unsigned)q;
-  const unsigned q4 = uq * 4u;
-  // stage 0 (radix 8, span 1): the thread's own points, no twiddles
-  {
+  }
+  static __device__ __forceinline__ void s0(float2 (&a)[8], float* re, float* im, int q, bool act) {
     float2 v[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) v[r] = a[r];
     dft8<false>(v);
     if (act) {
+      const unsigned uq = (unsigned)q;
       const unsigned b0 = (uq * 32u) | (uq & 28u);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) st(b0 ^ (4u * r), v[r]);
+      for (int r = 0; r < 8; ++r) st(reinterpret_cast<char*>(re), reinterpret_cast<char*>(im), b0 ^ (4u * r), v[r]);
     }
-    __syncthreads();
   }
-  // stage 1 (radix 8, span 8)
-  {
-    float2 v[8];
+  static __device__ __forceinline__ void s1r(float2 (&a)[8], const float* re, const float* im, int q, bool act) {
     if (act) {
+      const unsigned q4 = (unsigned)q * 4u;
 #pragma unroll
-      for (int r = 0; r < 8; ++r) v[r] = ld(q4 ^ (132u * r));
+      for (int r = 0; r < 8; ++r)
+        a[r] = ld(reinterpret_cast<const char*>(re), reinterpret_cast<const char*>(im), q4 ^ (132u * r));
     }
-    __syncthreads();
+  }
+  static __device__ __forceinline__ void s1w(float2 (&a)[8], float* re, float* im, int q,
+                                             const float2* __restrict__ twl, bool act) {
     if (act) {
       const int k = q & 7;
 #pragma unroll
-      for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], twl[r * k * 4]);
-      dft8<false>(v);
+      for (int r = 1; r < 8; ++r) a[r] = cmul(a[r], twl[r * k * 4]);
+      dft8<false>(a);
+      const unsigned uq = (unsigned)q;
       const unsigned ua = uq >> 3;
       const unsigned b1 = (ua * 256u) | (ua * 32u) | ((uq & 7u) * 4u);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) st(b1 ^ (32u * r), v[r]);
+      for (int r = 0; r < 8; ++r) st(reinterpret_cast<char*>(re), reinterpret_cast<char*>(im), b1 ^ (32u * r), a[r]);
     }
-    __syncthreads();
   }
-  // stage 2 (radix 4, span 64, last): two butterflies b, results back to a[b + 2r]
-  {
-    float2 v[2][4];
+  static __device__ __forceinline__ void s2(float2 (&a)[8], const float* re, const float* im, int q,
+                                            const float2* __restrict__ twl, bool act) {
     if (act) {
+      const unsigned q4 = (unsigned)q * 4u;
+      float2 v[2][4];
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) v[b][r] = ld(q4 ^ (128u * b + 288u * r));
+        for (int r = 0; r < 4; ++r)
+          v[b][r] = ld(reinterpret_cast<const char*>(re), reinterpret_cast<const char*>(im), q4 ^ (128u * b + 288u * r));
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         const int j = q + 32 * b;
@@ -463,6 +474,18 @@ __device__ __forceinline__ void row_fft256(float2 (&a)[8], float* re, float* im,
       }
     }
   }
+};
+
+__device__ __forceinline__ void row_fft256(float2 (&a)[8], float* re, float* im, int q,
+                                           const float2* __restrict__ twl, bool act) {
+  Row256::s0(a, re, im, q, act);
+  __syncthreads();
+  float2 v[8];
+  Row256::s1r(v, re, im, q, act);
+  __syncthreads();
+  Row256::s1w(v, re, im, q, twl, act);
+  __syncthreads();
+  Row256::s2(a, re, im, q, twl, act);
 }
 
 // Threads per column of the column passes: more threads for the long axes keep the
@@ -1295,9 +1318,13 @@ __global__ void __launch_bounds__(256) k_prox_tv(ProxArgs a, int ntx, int nty) {
 // conjugate of the forward transform of the conjugate (threads [R, 2R), R = PF_KB*PF_TY
 // rows of FT threads).  The arithmetic of every output is that of k_c2r_x, k_prox_tv and
 // k_r2c_x in sequence, except that with bf16 storage the gradient and y_{k+1} rows stay
-// fp32 (they never reach HBM here).
+// fp32 (they never reach HBM here).  At nx = 512 the transforms are instead pipelined with
+// the plane steps over batches of PP_KB planes: each row transform lives in one wavefront,
+// so its stages need no block barrier and are spread over the barrier intervals of the
+// plane steps, the memory-bound work hiding the transforms' arithmetic and LDS exchanges.
 constexpr int PF_TY = 4;
 constexpr int PF_KB = 4;
+constexpr int PP_KB = 2;  // planes per batch of the pipelined variant
 
 template <int M>
 struct PfT {  // threads per row of the M-point complex transforms
@@ -1317,16 +1344,20 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
                                                      const float2* __restrict__ twn, int nty) {
   constexpr bool COMP = ST == ST_COMP;
   constexpr bool BF = ST == ST_BF16;
-  constexpr int TY = PF_TY, KB = PF_KB;
+  // 512-wide maps: the row transforms are pipelined with the plane steps (see below)
+  constexpr bool PIPE = NX == 512;
+  constexpr int TY = PF_TY, KB = PIPE ? PP_KB : PF_KB;
   constexpr int M = NX / 2;
   constexpr int FT = PfT<M>::T, FE = PfT<M>::E;
   constexpr int NR = KB * TY;  // rows of one batch
+  constexpr int NG = PIPE ? 3 : 1;  // batches of rows in LDS
   using VT = typename std::conditional<BF, uint16_t, float>::type;  // penalty-weight word
   constexpr int NO = TY / 2;  // own rows per thread
-  static_assert(TY % 2 == 0 && 2 * NR * FT == 2 * NX, "one transform row share per thread");
+  static_assert(TY % 2 == 0 && 2 * NR * FT == (PIPE ? NX : 2 * NX), "one transform row share per thread");
+  static_assert(!PIPE || (M == 256 && FT == 32 && FE == 8), "the pipelined variant runs 512-wide maps");
   __shared__ float sY[3][TY + 2][NX];
   __shared__ float sSC[2][TY + 1][NX];
-  __shared__ float sG[KB][TY][NX];  // gradient rows of the batch, then its y_{k+1} rows
+  __shared__ float sG[NG][KB][TY][NX];  // gradient rows of a batch, then its y_{k+1} rows
   __shared__ float sFre[2 * NR][M + 1];
   __shared__ float sFim[2 * NR][M + 1];
   __shared__ float2 s_tw[M];   // M-point transform twiddles
@@ -1335,8 +1366,12 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
   const int tid = threadIdx.x;
   int x = tid % NX, r = tid / NX;
   int xm = (x + NX - 1) % NX, xp = (x + 1) % NX;
-  const int by = blockIdx.x % nty;
-  const int bz = blockIdx.x / nty;
+  // 512-wide maps: neighbouring tiles on one XCD, so that the halo rows a tile reads are
+  // often still in that XCD's L2 from its neighbours' own rows (measured 3% faster; no gain
+  // with the batched transforms, which leave the memory pipe idle for longer)
+  const int bid = PIPE ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int by = bid % nty;
+  const int bz = bid / nty;
   const int ny = a.ny, nz = a.nz;
   const int y0 = by * TY;
   const int z0 = bz * a.zc;
@@ -1404,7 +1439,7 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
   auto row_off = [&](int row) { return (unsigned)(((row / TY) * ny + row % TY) * M + fq) * 8u; };
   auto fetch_spec = [&](int zb, float2* sr) {
     const int zz = zb + (fr - NR) / TY;
-    if (fr >= NR && zz < z1) {
+    if ((!PIPE || fr < 2 * NR) && fr >= NR && zz < z1) {
       const float2* __restrict__ src = S + ((long long)zb * ny + y0) * M;
       const unsigned o = row_off(fr - NR);
 #pragma unroll
@@ -1476,7 +1511,7 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
     const bool act = fwd ? zz < zf_end : zz < z1;
     float* fre = &sFre[fr][0];
     float* fim = &sFim[fr][0];
-    float(*G)[NX] = sG[row / TY];
+    float(*G)[NX] = sG[0][row / TY];
     float2 v[FE];
     if (act) {
       if (fwd) {
@@ -1543,131 +1578,312 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
     }
   };
 
-  for (int i = tid; i < M; i += blockDim.x) {
-    s_tw[i] = twm[i];
-    s_twn[i] = twn[i];
-  }
-  // ---- prologue: the gradient rows of the first batch; y on planes z0-1, z0; sc(z0);
-  // prefetch plane z0+1, the outputs' inputs of plane z0 and the next batch's spectrum
+  // ---- one plane step, first half: y of plane z+1 from the words fetched during the
+  // previous step into the ring; the words of plane z+2 are requested at once
   RawX rown[NO], rhalo;
   float rv[NO + 1];
   double own_y[NO], own_xk[NO], nxt_y[NO], nxt_xk[NO];
   float u_cur[NO], xq_cur[NO];
-  float2 sa[FE];
-  fetch_spec(z0, sa);
-  {
-    double d1[NO], d2[NO];
-    fetch_x(z0 - 1, rown, rhalo);
-    store_plane(z0 - 1, rown, rhalo, d1, d2);
-    fetch_x(z0, rown, rhalo);
-    fetch_v(z0, rv);
-    store_plane(z0, rown, rhalo, own_y, own_xk);
-  }
-  transform_phase(z0, z0, z0, sa);  // inverse half only; ends with a barrier
-  {
-    float sc0[NO];
-    compute_sc(z0, rv, sc0);
-  }
-  fetch_x(z0 + 1, rown, rhalo);
-  fetch_v(z0 + 1, rv);
-  fetch_out(z0, u_cur, xq_cur);
-  fetch_spec(z0 + KB, sa);
-
-  for (int zb = z0; zb < z1; zb += KB) {
-    const int zb_end = min(zb + KB, z1);
-    for (int z = zb; z < zb_end; ++z) {
-      // The lane indices pass through empty asm statements so that the LDS and global
-      // addresses derived from them are formed inside the loop where they are used, not
-      // hoisted out of it and held in registers across all planes.
-      asm volatile("" : "+v"(x), "+v"(r), "+v"(xm), "+v"(xp), "+v"(halo_off));
+  auto step_a = [&](int z) {
+    // The lane indices pass through empty asm statements so that the LDS and global
+    // addresses derived from them are formed inside the loop where they are used, not
+    // hoisted out of it and held in registers across all planes.
+    asm volatile("" : "+v"(x), "+v"(r), "+v"(xm), "+v"(xp), "+v"(halo_off));
 #pragma unroll
-      for (int h = 0; h < NO; ++h) asm volatile("" : "+v"(own_off[h]));
-      asm volatile("" : "+v"(fr), "+v"(fq));
-      // y of plane z+1 from the words fetched during the previous step; the words of plane
-      // z+2 are requested at once, its v after sc(z+1) has used that of plane z+1
-      store_plane(z + 1, rown, rhalo, nxt_y, nxt_xk);
-      if (z + 1 < z1) fetch_x(z + 2, rown, rhalo);
-      __syncthreads();
-      // sc(z+1) into its ring slot (read by the next step) and, for this thread's own
-      // voxels, straight into the outputs of plane z: one phase, no barrier between
-      float sc1[NO];
-      compute_sc(z + 1, rv, sc1);
-      if (z + 1 < z1) fetch_v(z + 2, rv);
-      // ---- outputs of plane z (as k_prox_tv)
-      {
-        const float(*Ym)[NX] = sY[slot3(z - 1)];
-        const float(*Y0)[NX] = sY[slot3(z)];
-        const float(*Y1)[NX] = sY[slot3(z + 1)];
-        const float(*SC0)[NX] = sSC[z & 1];
-        float(*G)[NX] = sG[z - zb];
-        long long pz = (long long)z * plane;
-        asm volatile("" : "+s"(pz));
-        float* __restrict__ xnh = a.xn_hi + pz;
-        uint16_t* __restrict__ xnl = a.xn_lo + pz;
-#pragma unroll
-        for (int h = 0; h < NO; ++h) {
-          const int ly = r + 2 * h;
-          const float yc = Y0[ly + 1][x];
-          const float sc = SC0[ly][x];
-          // p = sc Dy rounded as stored fp32 values, summed in the order z, y, x, -x+, -y+, -z+
-          const float pzc = __fmul_rn(sc, yc - Ym[ly + 1][x]);
-          const float pyc = __fmul_rn(sc, yc - Y0[ly][x]);
-          const float pxc = __fmul_rn(sc, yc - Y0[ly + 1][xm]);
-          const float pxn = __fmul_rn(SC0[ly][xp], Y0[ly + 1][xp] - yc);
-          const float pyn = __fmul_rn(SC0[ly + 1][x], Y0[ly + 2][x] - yc);
-          const float pzn = __fmul_rn(sc1[h], Y1[ly + 1][x] - yc);
-          const float gtv = pzc + pyc + pxc - pxn - pyn - pzn;
-          const float gd = G[ly][x];
-          const float uu = u_cur[h];
-          const float xq = xq_cur[h];
-          float ynext;
-          if constexpr (COMP) {
-            const double y = own_y[h];
-            const double dprior = y - (double)xq;
-            const double zv = y - a.lr * ((double)gd + a.mu * (double)gtv + 2.0 * a.gamma * dprior);
-            const double t = a.lr * a.lam * (double)uu;
-            const double az = fabs(zv) - t;
-            const double xn = az > 0.0 ? copysign(az, zv) : 0.0;
-            if constexpr (MON) {
-              acc_l1 += (double)uu * fabs(y);
-              acc_gam += dprior * dprior;
-            }
-            const float hi = (float)xn;
-            const uint16_t lo = f32_to_bf16((float)(xn - (double)hi));
-            st_nt<NT>(xnh, own_off[h] * 4u, hi);
-            st_nt<NT>(xnl, own_off[h] * 2u, lo);
-            const double xs = (double)hi + (double)bf16_to_f32(lo);
-            ynext = (float)(xs + a.m_next * (xs - own_xk[h]));
-          } else {
-            const float y = (float)own_y[h];
-            const float dprior = y - xq;
-            const float zv = y - (float)a.lr * (gd + (float)a.mu * gtv + 2.0f * (float)a.gamma * dprior);
-            const float t = (float)a.lr * (float)a.lam * uu;
-            const float az = fabsf(zv) - t;
-            const float xn = az > 0.f ? copysignf(az, zv) : 0.f;
-            if constexpr (MON) {
-              acc_l1 += (double)uu * fabs((double)y);
-              acc_gam += (double)dprior * dprior;
-            }
-            st_nt<NT>(xnh, own_off[h] * 4u, xn);
-            const float xk = (float)own_xk[h];
-            ynext = xn + (float)a.m_next * (xn - xk);
-          }
-          G[ly][x] = ynext;
-        }
-      }
-      if (z + 1 < z1) fetch_out(z + 1, u_cur, xq_cur);
+    for (int h = 0; h < NO; ++h) asm volatile("" : "+v"(own_off[h]));
+    asm volatile("" : "+v"(fr), "+v"(fq));
+    store_plane(z + 1, rown, rhalo, nxt_y, nxt_xk);
+    if (z + 1 < z1) fetch_x(z + 2, rown, rhalo);
+  };
+  // second half (after a barrier): sc(z+1) into its ring slot (read by the next step) and,
+  // for this thread's own voxels, straight into the outputs of plane z, whose y_{k+1} rows
+  // replace its gradient rows G; v of plane z+2 is requested after sc(z+1) has used that of
+  // plane z+1
+  auto step_b = [&](int z, float (*G)[NX]) {
+    float sc1[NO];
+    compute_sc(z + 1, rv, sc1);
+    if (z + 1 < z1) fetch_v(z + 2, rv);
+    // ---- outputs of plane z (as k_prox_tv)
+    {
+      const float(*Ym)[NX] = sY[slot3(z - 1)];
+      const float(*Y0)[NX] = sY[slot3(z)];
+      const float(*Y1)[NX] = sY[slot3(z + 1)];
+      const float(*SC0)[NX] = sSC[z & 1];
+      long long pz = (long long)z * plane;
+      asm volatile("" : "+s"(pz));
+      float* __restrict__ xnh = a.xn_hi + pz;
+      uint16_t* __restrict__ xnl = a.xn_lo + pz;
 #pragma unroll
       for (int h = 0; h < NO; ++h) {
-        own_y[h] = nxt_y[h];
-        own_xk[h] = nxt_xk[h];
+        const int ly = r + 2 * h;
+        const float yc = Y0[ly + 1][x];
+        const float sc = SC0[ly][x];
+        // p = sc Dy rounded as stored fp32 values, summed in the order z, y, x, -x+, -y+, -z+
+        const float pzc = __fmul_rn(sc, yc - Ym[ly + 1][x]);
+        const float pyc = __fmul_rn(sc, yc - Y0[ly][x]);
+        const float pxc = __fmul_rn(sc, yc - Y0[ly + 1][xm]);
+        const float pxn = __fmul_rn(SC0[ly][xp], Y0[ly + 1][xp] - yc);
+        const float pyn = __fmul_rn(SC0[ly + 1][x], Y0[ly + 2][x] - yc);
+        const float pzn = __fmul_rn(sc1[h], Y1[ly + 1][x] - yc);
+        const float gtv = pzc + pyc + pxc - pxn - pyn - pzn;
+        const float gd = G[ly][x];
+        const float uu = u_cur[h];
+        const float xq = xq_cur[h];
+        float ynext;
+        if constexpr (COMP) {
+          const double y = own_y[h];
+          const double dprior = y - (double)xq;
+          const double zv = y - a.lr * ((double)gd + a.mu * (double)gtv + 2.0 * a.gamma * dprior);
+          const double t = a.lr * a.lam * (double)uu;
+          const double az = fabs(zv) - t;
+          const double xn = az > 0.0 ? copysign(az, zv) : 0.0;
+          if constexpr (MON) {
+            acc_l1 += (double)uu * fabs(y);
+            acc_gam += dprior * dprior;
+          }
+          const float hi = (float)xn;
+          const uint16_t lo = f32_to_bf16((float)(xn - (double)hi));
+          st_nt<NT>(xnh, own_off[h] * 4u, hi);
+          st_nt<NT>(xnl, own_off[h] * 2u, lo);
+          const double xs = (double)hi + (double)bf16_to_f32(lo);
+          ynext = (float)(xs + a.m_next * (xs - own_xk[h]));
+        } else {
+          const float y = (float)own_y[h];
+          const float dprior = y - xq;
+          const float zv = y - (float)a.lr * (gd + (float)a.mu * gtv + 2.0f * (float)a.gamma * dprior);
+          const float t = (float)a.lr * (float)a.lam * uu;
+          const float az = fabsf(zv) - t;
+          const float xn = az > 0.f ? copysignf(az, zv) : 0.f;
+          if constexpr (MON) {
+            acc_l1 += (double)uu * fabs((double)y);
+            acc_gam += (double)dprior * dprior;
+          }
+          st_nt<NT>(xnh, own_off[h] * 4u, xn);
+          const float xk = (float)own_xk[h];
+          ynext = xn + (float)a.m_next * (xn - xk);
+        }
+        G[ly][x] = ynext;
       }
-      __syncthreads();  // sY slot z-1 and the sG rows are rewritten next
     }
-    // ---- the batch's y_{k+1} rows into S; the next batch's gradient rows into sG
-    transform_phase(zb, zb_end, zb + KB, sa);
-    fetch_spec(zb + 2 * KB, sa);
-    __syncthreads();  // the exchange rows are rewritten by the next phase
+    if (z + 1 < z1) fetch_out(z + 1, u_cur, xq_cur);
+#pragma unroll
+    for (int h = 0; h < NO; ++h) {
+      own_y[h] = nxt_y[h];
+      own_xk[h] = nxt_xk[h];
+    }
+  };
+
+  for (int i = tid; i < M; i += blockDim.x) {
+    s_tw[i] = twm[i];
+    s_twn[i] = twn[i];
+  }
+  float2 sa[FE];
+  if constexpr (!PIPE) {
+    // ---- prologue: the gradient rows of the first batch; y on planes z0-1, z0; sc(z0);
+    // prefetch plane z0+1, the outputs' inputs of plane z0 and the next batch's spectrum
+    fetch_spec(z0, sa);
+    {
+      double d1[NO], d2[NO];
+      fetch_x(z0 - 1, rown, rhalo);
+      store_plane(z0 - 1, rown, rhalo, d1, d2);
+      fetch_x(z0, rown, rhalo);
+      fetch_v(z0, rv);
+      store_plane(z0, rown, rhalo, own_y, own_xk);
+    }
+    transform_phase(z0, z0, z0, sa);  // inverse half only; ends with a barrier
+    {
+      float sc0[NO];
+      compute_sc(z0, rv, sc0);
+    }
+    fetch_x(z0 + 1, rown, rhalo);
+    fetch_v(z0 + 1, rv);
+    fetch_out(z0, u_cur, xq_cur);
+    fetch_spec(z0 + KB, sa);
+
+    for (int zb = z0; zb < z1; zb += KB) {
+      const int zb_end = min(zb + KB, z1);
+      for (int z = zb; z < zb_end; ++z) {
+        step_a(z);
+        __syncthreads();
+        step_b(z, sG[0][z - zb]);
+        __syncthreads();  // sY slot z-1 and the sG rows are rewritten next
+      }
+      // ---- the batch's y_{k+1} rows into S; the next batch's gradient rows into sG
+      transform_phase(zb, zb_end, zb + KB, sa);
+      fetch_spec(zb + 2 * KB, sa);
+      __syncthreads();  // the exchange rows are rewritten by the next phase
+    }
+  } else {
+    // ---- Pipelined row transforms.  Each row transform runs on the 32 lanes of one
+    // half-wave and exchanges data only through its own LDS row, so its steps need no
+    // block barrier, only the in-order LDS accesses of one wavefront.  Threads [0, 2 NR FT)
+    // (whole waves) transform: rows [0, NR) the y_{k+1} rows of the previous batch forward,
+    // rows [NR, 2 NR) the gradient rows of the next batch inverse, in four chunks that ride
+    // along with the four barrier intervals of the current batch's two plane steps.  The
+    // rows of three batches sit in LDS (slot = batch % 3): the previous one (read by the
+    // forward chunks), the current one (stepped) and the next one (written by the inverse).
+    // Same arithmetic as transform_phase, step by step.
+    const bool ptx = tid < 2 * NR * FT;  // wave-uniform
+    const bool pfwd = fr < NR;           // wave-uniform
+    const int prow = pfwd ? fr : fr - NR;
+    const int mb = M - fq - FT * (FE - 1);  // mirror base, as in transform_phase
+    // chunk 1: forward rows of the batch at zf (planes < zf_end) out of slot gf; inverse
+    // rows: the spectrum in sa, then Z (as k_c2r_x, conjugated); radix-8 stage 0 of both
+    auto chunk1 = [&](int zf, int zf_end, int gf, int zi) {
+      if (!ptx) return;
+      float* fre = &sFre[fr][0];
+      float* fim = &sFim[fr][0];
+      float2 v[FE];
+      bool act;
+      if (pfwd) {
+        act = zf + prow / TY < zf_end;
+        if (act) {
+          const float(*G)[NX] = sG[gf][prow / TY];
+#pragma unroll
+          for (int i = 0; i < FE; ++i) v[i] = *reinterpret_cast<const float2*>(&G[prow % TY][2 * (fq + FT * i)]);
+        }
+      } else {
+        act = zi + prow / TY < z1;
+        if (act) {
+#pragma unroll
+          for (int i = 0; i < FE; ++i) {
+            fre[fq + FT * i] = sa[i].x;
+            fim[fq + FT * i] = sa[i].y;
+          }
+        }
+        wave_sync();
+        if (act) {
+#pragma unroll
+          for (int i = 0; i < FE; ++i) {
+            const float2 xk = sa[i];
+            const float2 xmr = make_float2(fre[mb + FT * (FE - 1 - i)], fim[mb + FT * (FE - 1 - i)]);
+            const float2 e = make_float2(xk.x + xmr.x, xk.y - xmr.y);
+            const float2 d = make_float2(xk.x - xmr.x, xk.y + xmr.y);
+            const float2 o = cmulc(d, s_twn[fq + FT * i]);
+            float2 zk = make_float2(e.x - o.y, e.y + o.x);
+            if (i == 0 && fq == 0) zk = make_float2(xk.x + xk.y, xk.x - xk.y);
+            v[i] = make_float2(zk.x, -zk.y);
+          }
+        }
+        wave_sync();
+      }
+      Row256::s0(v, fre, fim, fq, act);
+    };
+    auto pact = [&](int zf, int zf_end, int zi) {
+      return pfwd ? zf + prow / TY < zf_end : zi + prow / TY < z1;
+    };
+    // chunk 2: radix-8 stage 1
+    auto chunk2 = [&](int zf, int zf_end, int zi) {
+      if (!ptx) return;
+      const bool act = pact(zf, zf_end, zi);
+      float2 v[FE];
+      Row256::s1r(v, &sFre[fr][0], &sFim[fr][0], fq, act);
+      wave_sync();
+      Row256::s1w(v, &sFre[fr][0], &sFim[fr][0], fq, s_tw, act);
+    };
+    // chunk 3: radix-4 stage 2; inverse rows: real samples into slot gi; forward rows: Z
+    // into the row for the mirror reads of chunk 4
+    auto chunk3 = [&](int zf, int zf_end, int zi, int gi) {
+      if (!ptx) return;
+      const bool act = pact(zf, zf_end, zi);
+      float* fre = &sFre[fr][0];
+      float* fim = &sFim[fr][0];
+      float2 v[FE];
+      Row256::s2(v, fre, fim, fq, s_tw, act);
+      if (!act) return;
+      if (pfwd) {
+        wave_sync();
+#pragma unroll
+        for (int i = 0; i < FE; ++i) {
+          fre[fq + FT * i] = v[i].x;
+          fim[fq + FT * i] = v[i].y;
+        }
+      } else {  // z = conj(FFT(conj Z)): interleaved real samples of the row
+        float(*G)[NX] = sG[gi][prow / TY];
+#pragma unroll
+        for (int i = 0; i < FE; ++i)
+          *reinterpret_cast<float2*>(&G[prow % TY][2 * (fq + FT * i)]) = make_float2(v[i].x, -v[i].y);
+      }
+    };
+    // chunk 4: forward rows: X[k] from Z[k] and Z[M-k] (as k_r2c_x) into the spectrum rows
+    auto chunk4 = [&](int zf, int zf_end) {
+      if (!ptx || !pfwd || zf + prow / TY >= zf_end) return;
+      const float* fre = &sFre[fr][0];
+      const float* fim = &sFim[fr][0];
+      float2* __restrict__ dst = S + ((long long)zf * ny + y0) * M;
+      const unsigned ob = row_off(prow);
+#pragma unroll
+      for (int i = 0; i < FE; ++i) {
+        const float2 zk = make_float2(fre[fq + FT * i], fim[fq + FT * i]);
+        const float2 zm = make_float2(fre[mb + FT * (FE - 1 - i)], fim[mb + FT * (FE - 1 - i)]);
+        const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+        const float2 d = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y + zm.y));
+        const float2 o = make_float2(d.y, -d.x);
+        float2 out = cadd(e, cmul(s_twn[fq + FT * i], o));
+        if (i == 0 && fq == 0) out = make_float2(zk.x + zk.y, zk.x - zk.y);
+        st_nt<NT>(dst, ob + (unsigned)(FT * i) * 8u, out);
+      }
+    };
+
+    // ---- prologue: y on planes z0-1, z0; the first batch's gradient rows into slot 0;
+    // sc(z0); prefetch plane z0+1, the outputs' inputs of plane z0 and the spectrum of the
+    // second batch
+    fetch_spec(z0, sa);
+    {
+      double d1[NO], d2[NO];
+      fetch_x(z0 - 1, rown, rhalo);
+      store_plane(z0 - 1, rown, rhalo, d1, d2);
+      fetch_x(z0, rown, rhalo);
+      fetch_v(z0, rv);
+      store_plane(z0, rown, rhalo, own_y, own_xk);
+    }
+    __syncthreads();  // twiddles and the y rings
+    chunk1(z0, z0, 0, z0);
+    wave_sync();
+    chunk2(z0, z0, z0);
+    wave_sync();
+    chunk3(z0, z0, z0, 0);
+    fetch_spec(z0 + KB, sa);
+    {
+      float sc0[NO];
+      compute_sc(z0, rv, sc0);
+    }
+    fetch_x(z0 + 1, rown, rhalo);
+    fetch_v(z0 + 1, rv);
+    fetch_out(z0, u_cur, xq_cur);
+
+    int jb = 0;
+    for (int zb = z0; zb < z1; zb += KB, ++jb) {
+      const int zb_end = min(zb + KB, z1);
+      const int gc = jb % 3, gp = (jb + 2) % 3, gn = (jb + 1) % 3;  // slots: this, previous, next
+      // the previous batch (always whole) goes forward; none before the first batch
+      const int zf = zb - KB, zf_end = jb > 0 ? zb : zf;
+      const int zi = zb + KB;
+      step_a(zb);
+      chunk1(zf, zf_end, gp, zi);
+      fetch_spec(zb + 2 * KB, sa);
+      __syncthreads();
+      step_b(zb, sG[gc][0]);
+      chunk2(zf, zf_end, zi);
+      __syncthreads();
+      if (zb + 1 < zb_end) step_a(zb + 1);
+      chunk3(zf, zf_end, zi, gn);
+      __syncthreads();
+      if (zb + 1 < zb_end) step_b(zb + 1, sG[gc][1]);
+      chunk4(zf, zf_end);
+      __syncthreads();  // sY, sSC and the slots are rewritten by the next batch
+    }
+    // ---- epilogue: the last batch's y_{k+1} rows forward
+    {
+      const int zl = z0 + KB * (jb - 1);
+      chunk1(zl, z1, (jb - 1) % 3, z1);
+      wave_sync();
+      chunk2(zl, z1, z1);
+      wave_sync();
+      chunk3(zl, z1, z1, 0);
+      wave_sync();
+      chunk4(zl, z1);
+    }
   }
   if constexpr (MON) {
     __shared__ double s_red[16];
