@@ -1358,8 +1358,11 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
   __shared__ float sY[3][TY + 2][NX];
   __shared__ float sSC[2][TY + 1][NX];
   __shared__ float sG[NG][KB][TY][NX];  // gradient rows of a batch, then its y_{k+1} rows
-  __shared__ float sFre[2 * NR][M + 1];
-  __shared__ float sFim[2 * NR][M + 1];
+  __shared__ float sFre[PIPE ? 1 : 2 * NR][M + 1];
+  __shared__ float sFim[PIPE ? 1 : 2 * NR][M + 1];
+  // pipelined variant: the real and imaginary planes of a row 4M bytes apart (one address for
+  // both), plus one pad word past the last row
+  __shared__ float sFx[PIPE ? 2 * NR * 2 * M + 1 : 1];
   __shared__ float2 s_tw[M];   // M-point transform twiddles
   __shared__ float2 s_twn[M];  // W^k of the real-row pre- and post-processing
 
@@ -1731,8 +1734,8 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
     // rows: the spectrum in sa, then Z (as k_c2r_x, conjugated); radix-8 stage 0 of both
     auto chunk1 = [&](int zf, int zf_end, int gf, int zi) {
       if (!ptx) return;
-      float* fre = &sFre[fr][0];
-      float* fim = &sFim[fr][0];
+      float* fre = &sFx[fr * 2 * M];
+      float* fim = fre + M;
       float2 v[FE];
       bool act;
       if (pfwd) {
@@ -1777,17 +1780,18 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
       if (!ptx) return;
       const bool act = pact(zf, zf_end, zi);
       float2 v[FE];
-      Row256::s1r(v, &sFre[fr][0], &sFim[fr][0], fq, act);
+      float* fre = &sFx[fr * 2 * M];
+      Row256::s1r(v, fre, fre + M, fq, act);
       wave_sync();
-      Row256::s1w(v, &sFre[fr][0], &sFim[fr][0], fq, s_tw, act);
+      Row256::s1w(v, fre, fre + M, fq, s_tw, act);
     };
     // chunk 3: radix-4 stage 2; inverse rows: real samples into slot gi; forward rows: Z
     // into the row for the mirror reads of chunk 4
     auto chunk3 = [&](int zf, int zf_end, int zi, int gi) {
       if (!ptx) return;
       const bool act = pact(zf, zf_end, zi);
-      float* fre = &sFre[fr][0];
-      float* fim = &sFim[fr][0];
+      float* fre = &sFx[fr * 2 * M];
+      float* fim = fre + M;
       float2 v[FE];
       Row256::s2(v, fre, fim, fq, s_tw, act);
       if (!act) return;
@@ -1808,8 +1812,8 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
     // chunk 4: forward rows: X[k] from Z[k] and Z[M-k] (as k_r2c_x) into the spectrum rows
     auto chunk4 = [&](int zf, int zf_end) {
       if (!ptx || !pfwd || zf + prow / TY >= zf_end) return;
-      const float* fre = &sFre[fr][0];
-      const float* fim = &sFim[fr][0];
+      const float* fre = &sFx[fr * 2 * M];
+      const float* fim = fre + M;
       float2* __restrict__ dst = S + ((long long)zf * ny + y0) * M;
       const unsigned ob = row_off(prow);
 #pragma unroll
