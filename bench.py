@@ -376,12 +376,15 @@ def main():
     # One untimed step with HIP events around every kernel gives the per-kernel table and
     # names the dominant kernel; the timed steps record events around that kernel only
     # (events around all seven classes cost about 2% of the step time).
-    cap = rounds * (iters + 1) + 2
+    # (large maps run the y, z, y passes on four column ranges: four launches per pass)
+    cap = 4 * (rounds * (iters + 1) + 2)
     prof_all, dom = None, None
     if not args.no_profile:
         solver.profile_begin(None, cap)
         step()
         prof_all = solver.profile_end()
+        # a class that filled its event capacity would be undercounted
+        assert all(n < cap for _, n in prof_all.values()), prof_all
         dom = max(prof_all, key=lambda k: prof_all[k][0])
         solver.profile_begin(dom, args.steps * cap)
     torch.cuda.synchronize()
@@ -436,7 +439,10 @@ def main():
         kern = {}
         for k, (ms, n) in prof_all.items():
             if n:
+                # us_avg per launch; us_per_pass per pass over the map (a pass may be
+                # launched as several column ranges)
                 kern[k] = {"ms_total": ms, "launches": n, "us_avg": 1e3 * ms / n,
+                           "us_per_pass": 1e3 * ms / launches1[k] if launches1[k] else None,
                            "GBps": tot1[k] / (ms * 1e-3) / 1e9 if ms > 0 else None,
                            "model_launches": launches1[k]}
         line["kernels_profiled_step"] = kern

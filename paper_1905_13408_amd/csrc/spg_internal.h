@@ -69,11 +69,13 @@ hipError_t launch_prox_fft(const Dims& d, const ProxArgs& a, float2* S, const fl
                            int store, hipStream_t st, bool mon = false);
 
 // persist: the fused z modes run persistent blocks (false: one block per tile, for
-// problems that share the GPU with concurrent work)
+// problems that share the GPU with concurrent work).  kx0, nkx: the columns [kx0, kx0 + nkx)
+// of the packed spectrum only (nkx = 0: to the end of the row); the objective mode (3) takes
+// the whole row.
 hipError_t launch_fft_cols(const Dims& d, float2* S, int axis /*1 = y, 2 = z*/, int mode,
                            const float2* tw, const float* ws, const float2* cs, double* partials,
                            hipStream_t st, int* nblocks_out, int nt = 16 /* columns per tile: 8 or 16 */,
-                           bool persist = true);
+                           bool persist = true, int kx0 = 0, int nkx = 0);
 hipError_t launch_dc_nyquist(const Dims& d, float2* S, const float2* tw_z, const float* w0p,
                              const float* wnyq, const float2* c0p, const float2* cnyq, double* partials,
                              hipStream_t st, int* nblocks_out);

@@ -618,13 +618,15 @@ __global__ void __launch_bounds__(16 * ColT<L>::T) k_fft_cols(float2* __restrict
 
 // NTW: the folded weight and data term arrive by streaming loads (maps where they outgrow
 // the last-level cache; smaller maps keep them cached from one iteration to the next).
+// S and P describe the columns of this launch (a range of kx starting at column kxo of the
+// spectrum); Pw is the full row width, which lays out the folded weight and data term.
 template <int L, int MODE, bool NTW = false>
 __global__ void __launch_bounds__(16 * ColT<L>::T) k_fft_zw(float2* __restrict__ S, int P, int ntiles, int total,
                                                               long long pstride, long long bstride,
                                                               const float2* __restrict__ tw,
                                                               const float* __restrict__ ws,
                                                               const float2* __restrict__ cs,
-                                                              double* __restrict__ partials, int NT) {
+                                                              double* __restrict__ partials, int NT, int Pw, int kxo) {
   __shared__ float s_re[L * 16];
   __shared__ float s_im[L * 16];
   __shared__ float2 s_tw[L];
@@ -659,11 +661,11 @@ __global__ void __launch_bounds__(16 * ColT<L>::T) k_fft_zw(float2* __restrict__
   auto lane_off = [&](int tt) -> unsigned {
     return ((unsigned)((tt % ntiles) * NT + c < P ? c : 0) + (unsigned)q * ps) * 8u;
   };
-  // folded weight / data term: tile-major groups of WG = min(16, P) columns along z
-  const int WG = P < 16 ? P : 16;
+  // folded weight / data term: tile-major groups of WG = min(16, Pw) columns along z
+  const int WG = Pw < 16 ? Pw : 16;
   auto wc_base = [&](int tt) -> long long {
-    const int kx0 = (tt % ntiles) * NT;
-    return ((long long)(tt / ntiles) * (P / WG) + kx0 / WG) * L * WG + kx0 % WG;
+    const int kx0 = kxo + (tt % ntiles) * NT;
+    return ((long long)(tt / ntiles) * (Pw / WG) + kx0 / WG) * L * WG + kx0 % WG;
   };
   auto wc_off = [&](int tt) -> unsigned {  // element offset of the lane in its tile
     return (unsigned)((tt % ntiles) * NT + c < P ? c : 0) + (unsigned)(q * WG);
@@ -734,7 +736,7 @@ __global__ void __launch_bounds__(16 * ColT<L>::T) k_fft_zw(float2* __restrict__
     }
     reg_stages<L, T, 1, true>(a, re, im, NT, ql, s_tw);
 
-    if (valid && kx != 0) {  // the kx = 0 column belongs to k_dc_nyquist
+    if (valid && kx + kxo != 0) {  // the kx = 0 column belongs to k_dc_nyquist
       float2* __restrict__ Sb = S + ub;
 #pragma unroll
       for (int i = 0; i < E; ++i) st_at(Sb, o + i * step, a[i]);
@@ -784,6 +786,21 @@ __global__ void __launch_bounds__(256) k_dc_nyquist(float2* __restrict__ S, int 
     re[p * 2] = v.x;
     im[p * 2] = v.y;
   }
+  // the folded weights and data terms of the thread's points, requested before the forward
+  // transform so that their latency overlaps it
+  float w0v[NE], wnv[NE];
+  float2 c0v[NE], cnv[NE];
+#pragma unroll
+  for (int i = 0; i < NE; ++i) {
+    const int kz = q + T * i;
+    if (kz < L) {
+      const long long offn = (long long)myky * L + kz;
+      w0v[i] = w0p[offn];
+      wnv[i] = wnyq[offn];
+      c0v[i] = c0p ? c0p[offn] : make_float2(0.f, 0.f);
+      cnv[i] = cnyq ? cnyq[offn] : make_float2(0.f, 0.f);
+    }
+  }
   fft_lds<L, false, T>(re, im, 2, q, tw);
   float2 nv[NE];
   double acc = 0.0;
@@ -797,10 +814,8 @@ __global__ void __launch_bounds__(256) k_dc_nyquist(float2* __restrict__ S, int 
       const float2 A = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
       const float2 dd = make_float2(0.5f * (z1.x - z2.x), 0.5f * (z1.y + z2.y));
       const float2 B = make_float2(dd.y, -dd.x);
-      const long long offn = (long long)myky * L + kz;
-      const float w0 = w0p[offn], wn = wnyq[offn];
-      const float2 c0 = c0p ? c0p[offn] : make_float2(0.f, 0.f);
-      const float2 cn = cnyq ? cnyq[offn] : make_float2(0.f, 0.f);
+      const float w0 = w0v[i], wn = wnv[i];
+      const float2 c0 = c0v[i], cn = cnv[i];
       if constexpr (OBJ) {
         if (c == 0 || ky != kyp)
           acc += 0.5 * (double)w0 * ((double)A.x * A.x + (double)A.y * A.y) - ((double)c0.x * A.x + (double)c0.y * A.y) +
@@ -2517,7 +2532,7 @@ static int cu_count() {
 template <int L, int MODE, bool NTW>
 static hipError_t launch_zw(float2* S, int P, int ntiles, int total, long long pstride, long long bstride,
                             const float2* tw, const float* ws, const float2* cs, double* partials, int NT, int T,
-                            bool persist, hipStream_t st, int* nblocks_out) {
+                            bool persist, hipStream_t st, int* nblocks_out, int Pw, int kxo) {
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_fft_zw<L, MODE, NTW>, NT * T, 0) != hipSuccess || occ < 1)
     occ = 1;
@@ -2527,18 +2542,23 @@ static hipError_t launch_zw(float2* S, int P, int ntiles, int total, long long p
   else if (g >= 8) g &= ~7LL;
   if (nblocks_out) *nblocks_out = (int)g;
   k_fft_zw<L, MODE, NTW><<<dim3((unsigned)g), dim3(NT * T), 0, st>>>(S, P, ntiles, total, pstride, bstride, tw, ws, cs,
-                                                               partials, NT);
+                                                               partials, NT, Pw, kxo);
   return hipGetLastError();
 }
 
 hipError_t launch_fft_cols(const Dims& d, float2* S, int axis, int mode, const float2* tw, const float* ws,
                            const float2* cs, double* partials, hipStream_t st, int* nblocks_out, int nt,
-                           bool persist) {
+                           bool persist, int kx0, int nkx) {
   const int L = axis == 1 ? d.ny : d.nz;
   if (nt != 8 && nt != 16) return hipErrorInvalidValue;
   if (mode < 0 || mode > 4 || (mode >= 2 && axis != 2)) return hipErrorInvalidValue;
-  const int NT = d.P < nt ? d.P : nt;
-  const int ntiles = (d.P + NT - 1) / NT;
+  if (nkx == 0) nkx = d.P - kx0;
+  if (kx0 < 0 || nkx < 1 || kx0 + nkx > d.P || (kx0 > 0 && mode == 3)) return hipErrorInvalidValue;
+  // the columns [kx0, kx0 + nkx): tiles over that range, strides of the full spectrum
+  S += kx0;
+  const int Pc = nkx;
+  const int NT = Pc < nt ? Pc : nt;
+  const int ntiles = (Pc + NT - 1) / NT;
   const int nbatch = axis == 1 ? d.nz : d.ny;
   const long long pstride = axis == 1 ? (long long)d.P : (long long)d.ny * d.P;
   const long long bstride = axis == 1 ? (long long)d.ny * d.P : (long long)d.P;
@@ -2549,9 +2569,9 @@ hipError_t launch_fft_cols(const Dims& d, float2* S, int axis, int mode, const f
     const dim3 grid(total), block(NT * T);
     if (nblocks_out) *nblocks_out = total;
     if (mode == 0) {
-      SPG_DISPATCH_L(L, (k_fft_cols<L_, 0><<<grid, block, 0, st>>>(S, d.P, ntiles, pstride, bstride, tw, NT)));
+      SPG_DISPATCH_L(L, (k_fft_cols<L_, 0><<<grid, block, 0, st>>>(S, Pc, ntiles, pstride, bstride, tw, NT)));
     } else {
-      SPG_DISPATCH_L(L, (k_fft_cols<L_, 1><<<grid, block, 0, st>>>(S, d.P, ntiles, pstride, bstride, tw, NT)));
+      SPG_DISPATCH_L(L, (k_fft_cols<L_, 1><<<grid, block, 0, st>>>(S, Pc, ntiles, pstride, bstride, tw, NT)));
     }
     return hipGetLastError();
   }
@@ -2559,11 +2579,11 @@ hipError_t launch_fft_cols(const Dims& d, float2* S, int axis, int mode, const f
   // outgrow the 256 MiB last-level cache (measured at 512^3: 400 -> 391 us)
   const bool ntw = (double)d.nvox * 6.0 >= 256.0 * 1024 * 1024;
 #define SPG_ZW(MODE_) \
-  return launch_zw<L_, MODE_, false>(S, d.P, ntiles, total, pstride, bstride, tw, ws, cs, partials, NT, T, persist, \
-                                     st, nblocks_out)
+  return launch_zw<L_, MODE_, false>(S, Pc, ntiles, total, pstride, bstride, tw, ws, cs, partials, NT, T, persist, \
+                                     st, nblocks_out, d.P, kx0)
 #define SPG_ZWN(MODE_) \
-  return launch_zw<L_, MODE_, true>(S, d.P, ntiles, total, pstride, bstride, tw, ws, cs, partials, NT, T, persist, \
-                                    st, nblocks_out)
+  return launch_zw<L_, MODE_, true>(S, Pc, ntiles, total, pstride, bstride, tw, ws, cs, partials, NT, T, persist, \
+                                    st, nblocks_out, d.P, kx0)
   switch (mode) {
     case 2:
       if (ntw) {

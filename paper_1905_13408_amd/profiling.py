@@ -83,8 +83,11 @@ def summarize(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes, 
                 fv = [v for k, lst in fa.items() if k.startswith(prefix) and k.endswith("false>") for v in lst]
                 wv = [v for k, lst in wa.items() if k.startswith(prefix) and k.endswith("false>") for v in lst]
         if fv and wv:
+            # per launch, and in all (a pass over the map may be launched as several column
+            # ranges)
             out[cls] = {"launches": len(fv), "fetch_bytes": fs * sum(fv) / len(fv),
-                        "write_bytes": wsc * sum(wv) / len(wv)}
+                        "write_bytes": wsc * sum(wv) / len(wv),
+                        "fetch_bytes_total": fs * sum(fv), "write_bytes_total": wsc * sum(wv)}
     fused = any(k.startswith(FUSED) for k in fa)
     return {"command": command, "kernel_source_sha256": source_sha256(), "fetch_scale": fs, "write_scale": wsc,
             "copy_bytes_each_way": copy_bytes, "fused_x_transforms": fused, "per_launch": out}
