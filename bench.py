@@ -221,6 +221,14 @@ def batch_members(seed=0):
     return out
 
 
+def batch_roofline(members, shapes_tuned, iters, storage, sec_per_step):
+    tot = sum(schedule_iteration_bytes(tuple(int(v) for v in shape), 1, iters, storage, bool(tuned[3])) * iters
+              for (shape, _, _, _), tuned in zip(members, shapes_tuned))
+    ach = tot / sec_per_step / 1e9
+    return {"scope": "whole batch step (all members)", "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS, "traffic": None, "bytes_per_step": tot}
+
+
 def bench_batch(args):
     """8 volumes x `iters` SPG iterations: one HIP graph per step versus eager launches."""
     import torch
@@ -271,6 +279,10 @@ def bench_batch(args):
                                f"{iters} SPG iterations each", "storage": args.storage},
         "voxel_iterations_per_s": vox_it / res["graph"],
         "eager_ms_per_step": 1e3 * res["eager"],
+        # the whole batch step against 8 TB/s: every member's algorithmic bytes (one round from
+        # a zero map: uniform penalty weights, momentum from the third iteration); maps of
+        # 128^3-256^3 are partly served by the last-level cache, so this is an effective rate
+        "roofline": batch_roofline(members, shapes_tuned, iters, args.storage, res["graph"]),
         "graph_speedup_vs_eager": res["eager"] / res["graph"],
         "launch_shapes_nt_y_nt_z_zc_fused": shapes_tuned,
     }

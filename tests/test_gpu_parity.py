@@ -638,6 +638,32 @@ def test_batch_member_160_vs_oracle():
     batch.close()
 
 
+def test_batch_members_192_256_vs_oracle():
+    """The two largest boxes of the 8-volume batch workload, stepped together in one batch
+    graph, against the oracle at their own box sizes."""
+    members = []
+    for n, seed in ((192, 11), (256, 12)):
+        shape = (n, n, n)
+        announce(f"batch member {n}^3: inputs")
+        vol = synth.make_volume(shape, int(0.003 * n ** 3), max(1, int(0.003 * n ** 3) // 250), 1.2, 0.39 * n, 0.5,
+                                seed=seed, config_id=4, volume_id=n)
+        s = spg.SPGSolver(shape, 0.01, 0.05, 1e-3)
+        s.set_data(vol.w, vol.b)
+        s.set_map(None)
+        members.append((n, vol, s))
+    announce("batch members 192^3 + 256^3: 20 iterations in one graph")
+    batch = spg.SPGBatch([m[2] for m in members])
+    batch.run(20)
+    torch.cuda.synchronize()
+    for n, vol, s in members:
+        announce(f"batch member {n}^3: oracle (CPU)")
+        p = oracle_problem(vol.w, vol.b, 0.01, 0.05, 1e-3)
+        err = rel_l2(to_np(s.get_map()), O.spg_solve(p, 20))
+        print(f"{n}^3 batch member rel L2 = {err:.3e}", flush=True)
+        assert err < TOL
+    batch.close()
+
+
 # ------------------------------------------------------------------ backprojection (eq 24-29)
 
 @pytest.mark.parametrize("shape,m,n_img", [((32, 32, 32), 32, 40), ((16, 32, 64), 24, 25)])
