@@ -1967,6 +1967,33 @@ __global__ void k_fill(float* __restrict__ dst, long long n, float value) {
     dst[i] = value;
 }
 
+// Rows (kz, ky) of a [kz][ky][k] array with rows of len elements, spread over the blocks, and
+// the row's elements over a block's threads (several rows per pass where len < blockDim.x):
+// f(kz, ky, k) for every element, with no division per element.
+struct RowWalk {
+  unsigned tpr, rpi, lane, first, step, nrows;
+  __device__ RowWalk(int nz, int ny, int len) {
+    tpr = (unsigned)len < blockDim.x ? (unsigned)len : blockDim.x;
+    rpi = blockDim.x / tpr;
+    const unsigned sub = threadIdx.x / tpr;
+    lane = threadIdx.x - sub * tpr;
+    nrows = sub < rpi ? (unsigned)nz * (unsigned)ny : 0u;  // threads past the last whole row idle
+    first = blockIdx.x * rpi + sub;
+    step = gridDim.x * rpi;
+  }
+};
+// SPG_ROWS(w, kz, ky, k, nz, ny, len) { body }: the body runs for each element (kz, ky, k) of
+// the rows that this thread's block and lane walk (the middle loop only binds kz and ky)
+#define SPG_ROWS(W, KZ, KY, K, NZ, NY, LEN)                                                   \
+  RowWalk W(NZ, NY, LEN);                                                                     \
+  for (unsigned row_ = W.first; row_ < W.nrows; row_ += W.step)                               \
+    for (int KZ = (int)(row_ / (unsigned)(NY)), KY = (int)(row_ - (unsigned)KZ * (unsigned)(NY)), \
+             K = (int)W.lane, once_ = 1;                                                      \
+         once_; once_ = 0)                                                                    \
+      for (; K < (LEN); K += (int)W.tpr)
+// index of -k on an axis of n points
+__device__ __forceinline__ int neg_mod(int k, int n) { return k == 0 ? 0 : n - k; }
+
 // Fold of the data term onto the packed half spectrum (a real map only sees the
 // Hermitian part of w (A x - b)):  w~ = (w_k + w_{-k})/2,  c = (w_k b_k + w_{-k} conj b_{-k})/2,
 // stored scaled for unnormalised transforms: ws = w~ / nvox, cs = c / sqrt(nvox).
@@ -1988,16 +2015,11 @@ __global__ void __launch_bounds__(256) k_fold(Dims d, const float* __restrict__ 
                                               double* __restrict__ partials) {
   __shared__ double s_red[8];
   const int P = d.P;
-  const long long nh = (long long)d.nz * d.ny * (P + 1);
   const double inv_n = 1.0 / (double)d.nvox;
   const double inv_sqrt_n = 1.0 / sqrt((double)d.nvox);
-  double mx = 0.0;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nh; t += (long long)gridDim.x * blockDim.x) {
-    const int kx = (int)(t % (P + 1));
-    const long long r = t / (P + 1);
-    const int ky = (int)(r % d.ny);
-    const int kz = (int)(r / d.ny);
-    const int nkx = (d.nx - kx) % d.nx, nky = (d.ny - ky) % d.ny, nkz = (d.nz - kz) % d.nz;
+  // one element of the folded half spectrum; returns w~ (unscaled) for the maximum
+  auto fold = [=](int kz, int ky, int kx) -> double {
+    const int nkx = neg_mod(kx, d.nx), nky = neg_mod(ky, d.ny), nkz = neg_mod(kz, d.nz);
     const long long ik = ((long long)kz * d.ny + ky) * d.nx + kx;
     const long long in = ((long long)nkz * d.ny + nky) * d.nx + nkx;
     const double wk = w[ik], wn = w[in];
@@ -2005,7 +2027,6 @@ __global__ void __launch_bounds__(256) k_fold(Dims d, const float* __restrict__ 
     const double wt = 0.5 * (wk + wn);
     const double cr = 0.5 * (wk * bk.x + wn * bn.x);
     const double ci = 0.5 * (wk * bk.y - wn * bn.y);
-    mx = wt > mx ? wt : mx;
     const float wsv = (float)(wt * inv_n);
     const float2 csv = make_float2((float)(cr * inv_sqrt_n), (float)(ci * inv_sqrt_n));
     const long long op = (long long)ky * d.nz + kz;  // [ky][kz] planes of kx = 0 and nx/2
@@ -2021,6 +2042,19 @@ __global__ void __launch_bounds__(256) k_fold(Dims d, const float* __restrict__ 
       wnyq[op] = wsv;
       cnyq[op] = csv;
     }
+    return wt;
+  };
+  double mx = 0.0;
+  // columns kx < P row by row, then the column kx = P (= nx/2) one row per thread
+  SPG_ROWS(rw, kz, ky, kx, d.nz, d.ny, P) {
+    const double wt = fold(kz, ky, kx);
+    mx = wt > mx ? wt : mx;
+  }
+  const unsigned nrows = (unsigned)d.nz * (unsigned)d.ny;
+  for (unsigned row = blockIdx.x * blockDim.x + threadIdx.x; row < nrows; row += gridDim.x * blockDim.x) {
+    const int kz = (int)(row / (unsigned)d.ny), ky = (int)(row - (unsigned)kz * (unsigned)d.ny);
+    const double wt = fold(kz, ky, P);
+    mx = wt > mx ? wt : mx;
   }
   const double r = block_reduce<RED_OP_MAX>(mx, s_red);
   if (threadIdx.x == 0) partials[blockIdx.x] = r;
@@ -2035,8 +2069,8 @@ __global__ void __launch_bounds__(256) k_data_stats(Dims d, const float* __restr
                                                     const float2* __restrict__ b, double* __restrict__ partials) {
   __shared__ double s_red[8];
   double bad = 0.0, mn = 1e300, c0 = 0.0, sw = 0.0, eh = 0.0;
-  const long long n = d.nvox, plane = (long long)d.nx * d.ny;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+  SPG_ROWS(rw, kz, ky, kx, d.nz, d.ny, d.nx) {
+    const long long i = ((long long)kz * d.ny + ky) * d.nx + kx;
     const float wv = w[i];
     const float2 bv = b[i];
     const bool fin = isfinite(wv) && isfinite(bv.x) && isfinite(bv.y);
@@ -2045,9 +2079,7 @@ __global__ void __launch_bounds__(256) k_data_stats(Dims d, const float* __restr
       mn = wv < mn ? wv : mn;
       c0 += 0.5 * (double)wv * ((double)bv.x * bv.x + (double)bv.y * bv.y);
       sw += (double)wv;
-      const int kx = (int)(i % d.nx), ky = (int)((i / d.nx) % d.ny), kz = (int)(i / plane);
-      const long long j = (long long)((d.nz - kz) % d.nz) * plane + (long long)((d.ny - ky) % d.ny) * d.nx +
-                          (d.nx - kx) % d.nx;
+      const long long j = ((long long)neg_mod(kz, d.nz) * d.ny + neg_mod(ky, d.ny)) * d.nx + neg_mod(kx, d.nx);
       const float wm = w[j];
       const float2 bm = b[j];
       const double px = wv > 0.f ? (double)bv.x : 0.0, py = wv > 0.f ? (double)bv.y : 0.0;
@@ -2103,11 +2135,8 @@ __global__ void __launch_bounds__(256) k_reweight(Dims d, const float* __restric
   __shared__ double s_red[8];
   double mx = 0.0, l1 = 0.0, l2 = 0.0;
   const long long plane = (long long)d.nx * d.ny;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < d.nvox;
-       i += (long long)gridDim.x * blockDim.x) {
-    const int x = (int)(i % d.nx);
-    const int y = (int)((i / d.nx) % d.ny);
-    const int z = (int)(i / plane);
+  SPG_ROWS(rw, z, y, x, d.nz, d.ny, d.nx) {
+    const long long i = ((long long)z * d.ny + y) * d.nx + x;
     const long long ixm = i - x + (x == 0 ? d.nx - 1 : x - 1);
     const long long iym = i + (long long)((y == 0 ? d.ny - 1 : y - 1) - y) * d.nx;
     const long long izm = i + (long long)((z == 0 ? d.nz - 1 : z - 1) - z) * plane;
