@@ -387,17 +387,6 @@ __device__ __forceinline__ void fft_reg(float2 (&a)[reg_e(L, TT)], float* re, fl
   reg_stages<L, TT, 0, INV, RegPlan<L, TT>::ns, SWZ>(a, re, im, ps, q, twl, act);
 }
 
-// fft_reg<256, false, 32, true> (the 512-point real rows of a 512-wide map) with its LDS
-// positions written out: stages radix 8, 8, 4 over the points q + 32 i of thread q < 32.
-// The swizzled position of each stage's element reduces, because q < 32, to a per-thread
-// base XOR a constant (bytes):
-//   stage 0 writes 8q + (r ^ (q >> 2))            -> (32q | 4(q >> 2)) ^ 4r
-//   stage 1 reads  (q + 32r) ^ r = q ^ 33r        -> 4q ^ 132r
-//   stage 1 writes 64a + (q & 7) + 8(r ^ a), a = q >> 3 -> (256a | 32a | 4(q & 7)) ^ 32r
-//   stage 2 reads  (q + 32b + 64r) ^ 8r           -> 4q ^ (128b + 288r)
-// so each access costs one XOR and one add of the row base instead of the generic index
-// arithmetic.  Same twiddles, products and butterflies as the generic stages, so the results
-// are bitwise those of fft_reg.
 // Orders the LDS accesses of one wavefront across this point.  A wavefront executes its LDS
 // instructions in order, so data exchanged among its own lanes needs no s_barrier; this only
 // keeps the compiler from moving accesses across.
@@ -407,8 +396,18 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The stages of row_fft256, for callers that interleave them with other work (the barriers
-// between them are the caller's): s0 transforms the thread's own points and writes them, s1r
+// fft_reg<256, false, 32, true> (the 512-point real rows of a 512-wide map) with its LDS
+// positions written out, in stages for callers that interleave them with other work (the
+// ordering between stages is the caller's: wave_sync where one wavefront holds the row).
+// Stages radix 8, 8, 4 over the points q + 32 i of thread q < 32.  The swizzled position of
+// each stage's element reduces, because q < 32, to a per-thread base XOR a constant (bytes):
+//   stage 0 writes 8q + (r ^ (q >> 2))            -> (32q | 4(q >> 2)) ^ 4r
+//   stage 1 reads  (q + 32r) ^ r = q ^ 33r        -> 4q ^ 132r
+//   stage 1 writes 64a + (q & 7) + 8(r ^ a), a = q >> 3 -> (256a | 32a | 4(q & 7)) ^ 32r
+//   stage 2 reads  (q + 32b + 64r) ^ 8r           -> 4q ^ (128b + 288r)
+// so each access costs one XOR and one add of the row base instead of the generic index
+// arithmetic.  Same twiddles, products and butterflies as the generic stages, so the results
+// are bitwise those of fft_reg.  s0 transforms the thread's own points and writes them, s1r
 // reads the stage-1 inputs, s1w twiddles, transforms and writes them, s2 reads, twiddles and
 // transforms the last stage back into a[b + 2r].
 struct Row256 {
@@ -475,18 +474,6 @@ struct Row256 {
     }
   }
 };
-
-__device__ __forceinline__ void row_fft256(float2 (&a)[8], float* re, float* im, int q,
-                                           const float2* __restrict__ twl, bool act) {
-  Row256::s0(a, re, im, q, act);
-  __syncthreads();
-  float2 v[8];
-  Row256::s1r(v, re, im, q, act);
-  __syncthreads();
-  Row256::s1w(v, re, im, q, twl, act);
-  __syncthreads();
-  Row256::s2(a, re, im, q, twl, act);
-}
 
 // Threads per column of the column passes: more threads for the long axes keep the
 // per-thread state of the fused z pass (data, folded weight and data term) small.  At
@@ -1562,8 +1549,7 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
       }
     }
     __syncthreads();
-    if constexpr (M == 256 && FT == 32) row_fft256(v, fre, fim, fq, s_tw, act);
-    else fft_reg<M, false, FT, true>(v, fre, fim, 1, fq, s_tw, act);
+    fft_reg<M, false, FT, true>(v, fre, fim, 1, fq, s_tw, act);
     if (act && !fwd) {  // z = conj(FFT(conj Z)): interleaved real samples of the row
 #pragma unroll
       for (int i = 0; i < FE; ++i)
