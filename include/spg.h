@@ -223,7 +223,7 @@ spg_status spg_set_launch_shape(spg_problem* P, int32_t nt_y, int32_t nt_z, int3
 spg_status spg_get_launch_shape(const spg_problem* P, int32_t* nt_y, int32_t* nt_z, int32_t* zc);
 spg_status spg_autotune(spg_problem* P, int32_t iters);
 
-/* Fused x-axis transforms (on by default where supported: nx in {64, 128, 256, 512} and
+/* Fused x-axis transforms (on by default where supported: nx in {32, 64, 128, 256, 512} and
  * ny a multiple of 4).  An iteration then reads the data gradient as the rows of its
  * packed x-spectrum and writes the x-spectrum of the next extrapolated map from the
  * stencil/prox kernel itself, on tiles of 4 full-width rows, instead of running separate

@@ -59,7 +59,7 @@ int prox_num_blocks(const Dims& d, int zc);
 
 // Fused x-axis transforms + stencil/prox on full-width rows: reads the gradient as the
 // packed x-spectrum rows in S (after the y and z passes), writes x_{k+1} and the
-// x-spectrum of y_{k+1} back into S.  Grids with nx in {64, 128, 256, 512} and ny a
+// x-spectrum of y_{k+1} back into S.  Grids with nx in {32, 64, 128, 256, 512} and ny a
 // multiple of 4 (the kernel's tile height).
 bool prox_fft_supported(const Dims& d);
 int prox_fft_num_blocks(const Dims& d, int zc);

@@ -2696,7 +2696,8 @@ static dim3 ew_grid(long long n) {
 }
 
 bool prox_fft_supported(const Dims& d) {
-  return (d.nx == 64 || d.nx == 128 || d.nx == 256 || d.nx == 512) && d.ny >= PF_TY && d.ny % PF_TY == 0;
+  return (d.nx == 32 || d.nx == 64 || d.nx == 128 || d.nx == 256 || d.nx == 512) && d.ny >= PF_TY &&
+         d.ny % PF_TY == 0;
 }
 
 int prox_fft_num_blocks(const Dims& d, int zc) { return (d.ny / PF_TY) * ((d.nz + zc - 1) / zc); }
@@ -2725,6 +2726,7 @@ hipError_t launch_prox_fft(const Dims& d, const ProxArgs& a, float2* S, const fl
     default: SPG_PF2(NX_, ST_BF16); break;            \
   }
   switch (d.nx) {
+    case 32: SPG_PF(32); break;
     case 64: SPG_PF(64); break;
     case 128: SPG_PF(128); break;
     case 256: SPG_PF(256); break;

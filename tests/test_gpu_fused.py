@@ -2,7 +2,7 @@
 rows and writes the x-spectrum of the next extrapolated map) against the separate sweeps
 and against the FP64 oracle: same iterates up to rounding, every storage mode, ragged
 z-slabs (zc not dividing nz), one-tile rows (ny = 4), the gamma term's prior map.  (The parity tests of the
-solver on grids with nx in {64, 128, 256, 512} run the fused path by default; those with
+solver on grids with nx in {32, 64, 128, 256, 512} run the fused path by default; those with
 other nx run the separate sweeps.)"""
 import numpy as np
 import pytest
@@ -44,7 +44,8 @@ def _solve(shape, storage, fused, K, zc, seed, lam=0.02, mu=0.05, eps=1e-2, prio
     return to_np(s.get_map()), s
 
 
-@pytest.mark.parametrize("shape,zc", [((32, 160, 64), 5), ((16, 8, 128), 5), ((8, 4, 512), 5), ((16, 16, 256), 32)])
+@pytest.mark.parametrize("shape,zc", [((32, 160, 64), 5), ((16, 8, 128), 5), ((8, 4, 512), 5), ((16, 16, 256), 32),
+                                      ((16, 8, 32), 5)])
 @pytest.mark.parametrize("storage", ["compensated", "fp32"])
 def test_fused_equals_separate_sweeps(shape, zc, storage):
     announce(f"fused vs separate shape={shape} zc={zc} storage={storage}")
@@ -96,7 +97,8 @@ def test_fusion_switch_follows_grid_support():
     assert spg.SPGSolver((8, 8, 64), 0.01, 0.05, 1e-2).fusion
     assert spg.SPGSolver((8, 4, 512), 0.01, 0.05, 1e-2).fusion
     assert spg.SPGSolver((4, 160, 256), 0.01, 0.05, 1e-2).fusion
-    for shape in [(8, 8, 32), (8, 8, 160), (8, 8, 16)]:
+    assert spg.SPGSolver((8, 8, 32), 0.01, 0.05, 1e-2).fusion
+    for shape in [(8, 8, 160), (8, 8, 16), (8, 8, 192)]:
         s = spg.SPGSolver(shape, 0.01, 0.05, 1e-2)
         assert not s.fusion
         with pytest.raises(RuntimeError):
