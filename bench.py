@@ -509,6 +509,7 @@ def bench_small(args):
     iters = args.iters or c["iters"]
     s = spg.SPGSolver(c["shape"], c["lam"], c["mu"], c["eps"], storage=args.storage)
     s.set_data(torch.from_numpy(vol.w).cuda(), torch.from_numpy(vol.b).cuda())
+    launch_shape = s.launch_shape() if args.no_autotune else s.autotune(8)
     batch = spg.SPGBatch([s])
     res = {}
     for name, run in [("eager", lambda: s.run(iters)), ("graph", lambda: batch.run(iters))]:
@@ -533,6 +534,7 @@ def bench_small(args):
                    "storage": args.storage},
         "graph_iterations_per_s": iters / res["graph"],
         "graph_speedup_vs_eager": res["eager"] / res["graph"],
+        "launch_shape_nt_y_nt_z_zc": list(launch_shape), "x_transforms": "fused" if s.fusion else "separate",
         "step": "set_map + the iterations, launched eagerly (graph: one HIP graph of all of them, replayed)",
     }
     print(json.dumps(line))

@@ -214,11 +214,13 @@ spg_status spg_set_state(spg_problem* P, const void* d_buf, size_t bytes);
 /* Launch shapes: columns per tile of the y and z transform passes (8 or 16) and the z-slab
  * depth of the stencil kernel (4..512 planes).  spg_autotune times each knob in turn
  * (coordinate search over {16, 8}, {16, 8}, fused x transforms {on, off} when they are on
- * (see spg_set_fusion), {32, 16, 64, 128, 256}) on `iters` iterations (after three
+ * (see spg_set_fusion), {32, 16, 64, 128, 256, 8, 4}) on `iters` iterations (after three
  * untimed ones, so that the momentum term is active) from the zero map, with the penalty
  * weights as set, with HIP events, each candidate twice (two sweeps, the faster time
  * counts), and keeps the fastest; it leaves the map at 0 with the momentum restarted.
- * Results are bitwise independent of the launch shape. */
+ * Defaults: 16, 16 and a slab depth of 32 planes, halved (down to 4) while the stencil
+ * kernel would run fewer than 512 blocks (small maps).  Results are bitwise independent of
+ * the launch shape. */
 spg_status spg_set_launch_shape(spg_problem* P, int32_t nt_y, int32_t nt_z, int32_t zc);
 spg_status spg_get_launch_shape(const spg_problem* P, int32_t* nt_y, int32_t* nt_z, int32_t* zc);
 spg_status spg_autotune(spg_problem* P, int32_t iters);

@@ -295,32 +295,41 @@ spg_status gradient_pipeline(spg_problem* P, bool obj, int* nA, int* nB, void* g
   const float2* twz = P->at<float2>(P->lay.tw_z);
   const float* wsp = P->at<float>(P->lay.ws);
   const float2* csp = P->at<float2>(P->lay.cs);
-  // Where the spectrum outgrows the 256 MiB last-level cache, the y, z, y passes run on four
-  // column ranges (kx quarters) in turn, so that each pass reads what the previous one just
-  // wrote while it is still cached (measured at 512^3: 1.3% more iterations/s, most of it in
-  // the stencil kernel that follows).  The objective variant of the z pass takes whole rows.
-  const int nch = (!obj && (double)d.nvox * 4.0 >= 256.0 * 1024 * 1024 && d.P % 64 == 0) ? 4 : 1;
-  const int cw = d.P / nch;
-  for (int c = 0; c < nch; ++c) {
-    const int kx0 = c * cw, nkx = nch > 1 ? cw : 0;
-    prof_begin(P, SPG_KERNEL_FFT_Y_FWD);
-    SPG_CK(P, launch_fft_cols(d, P->S(), 1, 0, twy, nullptr, nullptr, nullptr, st, nullptr, P->nt_y, true, kx0, nkx));
-    prof_end(P, SPG_KERNEL_FFT_Y_FWD);
+  if (!obj && yz_plane_supported(d)) {
+    // small maps: the y, z (with the weight step and the packed plane) and y inverse passes
+    // in one launch, timed as the z pass
     prof_begin(P, SPG_KERNEL_FFT_Z_WEIGHT);
-    // the objective variant writes one partial per block: 16-column tiles keep <= 8192 blocks
-    SPG_CK(P, launch_fft_cols(d, P->S(), 2, obj ? 3 : 2, twz, wsp, csp, obj ? P->part() + kPartA : nullptr, st, nA,
-                              obj ? 16 : P->nt_z, !P->shared_gpu, kx0, nkx));
+    SPG_CK(P, launch_yz_plane(d, P->S(), twy, twz, wsp, csp, P->at<float>(P->lay.w0p), P->at<float>(P->lay.wnyq),
+                              P->at<float2>(P->lay.c0p), P->at<float2>(P->lay.cnyq), st));
     prof_end(P, SPG_KERNEL_FFT_Z_WEIGHT);
-    if (c == 0) {  // the packed kx = 0 / nx/2 plane
-      prof_begin(P, SPG_KERNEL_DC_NYQUIST);
-      SPG_CK(P, launch_dc_nyquist(d, P->S(), twz, P->at<float>(P->lay.w0p), P->at<float>(P->lay.wnyq),
-                                  P->at<float2>(P->lay.c0p), P->at<float2>(P->lay.cnyq),
-                                  obj ? P->part() + kPartB : nullptr, st, nB));
-      prof_end(P, SPG_KERNEL_DC_NYQUIST);
+  } else {
+    // Where the spectrum outgrows the 256 MiB last-level cache, the y, z, y passes run on four
+    // column ranges (kx quarters) in turn, so that each pass reads what the previous one just
+    // wrote while it is still cached (measured at 512^3: 1.3% more iterations/s, most of it in
+    // the stencil kernel that follows).  The objective variant of the z pass takes whole rows.
+    const int nch = (!obj && (double)d.nvox * 4.0 >= 256.0 * 1024 * 1024 && d.P % 64 == 0) ? 4 : 1;
+    const int cw = d.P / nch;
+    for (int c = 0; c < nch; ++c) {
+      const int kx0 = c * cw, nkx = nch > 1 ? cw : 0;
+      prof_begin(P, SPG_KERNEL_FFT_Y_FWD);
+      SPG_CK(P, launch_fft_cols(d, P->S(), 1, 0, twy, nullptr, nullptr, nullptr, st, nullptr, P->nt_y, true, kx0, nkx));
+      prof_end(P, SPG_KERNEL_FFT_Y_FWD);
+      prof_begin(P, SPG_KERNEL_FFT_Z_WEIGHT);
+      // the objective variant writes one partial per block: 16-column tiles keep <= 8192 blocks
+      SPG_CK(P, launch_fft_cols(d, P->S(), 2, obj ? 3 : 2, twz, wsp, csp, obj ? P->part() + kPartA : nullptr, st, nA,
+                                obj ? 16 : P->nt_z, !P->shared_gpu, kx0, nkx));
+      prof_end(P, SPG_KERNEL_FFT_Z_WEIGHT);
+      if (c == 0) {  // the packed kx = 0 / nx/2 plane
+        prof_begin(P, SPG_KERNEL_DC_NYQUIST);
+        SPG_CK(P, launch_dc_nyquist(d, P->S(), twz, P->at<float>(P->lay.w0p), P->at<float>(P->lay.wnyq),
+                                    P->at<float2>(P->lay.c0p), P->at<float2>(P->lay.cnyq),
+                                    obj ? P->part() + kPartB : nullptr, st, nB));
+        prof_end(P, SPG_KERNEL_DC_NYQUIST);
+      }
+      prof_begin(P, SPG_KERNEL_FFT_Y_INV);
+      SPG_CK(P, launch_fft_cols(d, P->S(), 1, 1, twy, nullptr, nullptr, nullptr, st, nullptr, P->nt_y, true, kx0, nkx));
+      prof_end(P, SPG_KERNEL_FFT_Y_INV);
     }
-    prof_begin(P, SPG_KERNEL_FFT_Y_INV);
-    SPG_CK(P, launch_fft_cols(d, P->S(), 1, 1, twy, nullptr, nullptr, nullptr, st, nullptr, P->nt_y, true, kx0, nkx));
-    prof_end(P, SPG_KERNEL_FFT_Y_INV);
   }
   if (!x_inverse) return SPG_OK;
   prof_begin(P, SPG_KERNEL_C2R_X);
@@ -419,6 +428,10 @@ spg_status spg_create(const spg_params* p, void* d_workspace, size_t bytes, void
   P->store = P->comp ? ST_COMP : ((p->flags & SPG_FLAG_BF16_STORAGE) ? ST_BF16 : ST_PLAIN);
   P->dn2 = dnorm2_of(p->nx, p->ny, p->nz);
   P->fused = prox_fft_supported(P->d);
+  // z-slab depth of the stencil kernel: 32 planes, or fewer on small maps, whose blocks
+  // (ny / 4 tiles per slab) would otherwise be too few to keep more than a few CUs busy and
+  // each march through many planes in turn
+  while (P->zc > 4 && (long long)(p->ny / 4) * ((p->nz + P->zc - 1) / P->zc) < 512) P->zc /= 2;
   P->mon_every = (p->flags & SPG_FLAG_MONITOR) ? p->obj_every : 0;
   P->hist_iter.assign(kHistCap, 0);
   restart(P);
@@ -1015,7 +1028,7 @@ spg_status spg_autotune(spg_problem* P, int32_t iters) {
   std::vector<Knob> knobs = {{&P->nt_y, {SPG_KERNEL_FFT_Y_FWD}, {16, 8}},
                              {&P->nt_z, {SPG_KERNEL_FFT_Z_WEIGHT}, {16, 8}}};
   if (P->fused) knobs.push_back({&fused, {SPG_KERNEL_PROX_TV, SPG_KERNEL_C2R_X, SPG_KERNEL_R2C_X}, {1, 0}});
-  knobs.push_back({&P->zc, {SPG_KERNEL_PROX_TV}, {32, 16, 64, 128, 256}});
+  knobs.push_back({&P->zc, {SPG_KERNEL_PROX_TV}, {32, 16, 64, 128, 256, 8, 4}});
   // Each candidate is timed twice, in two sweeps over the candidates, and keeps the faster of
   // its two times, so that one slow sample on a busy GPU does not decide.  A pass may be
   // launched as several column ranges: the event capacity covers four launches per class

@@ -76,6 +76,12 @@ hipError_t launch_fft_cols(const Dims& d, float2* S, int axis /*1 = y, 2 = z*/, 
                            const float2* tw, const float* ws, const float2* cs, double* partials,
                            hipStream_t st, int* nblocks_out, int nt = 16 /* columns per tile: 8 or 16 */,
                            bool persist = true, int kx0 = 0, int nkx = 0);
+// Small maps (ny, nz in {8, 16, 32, 64}): the y forward, z + weight + packed-plane and y inverse
+// passes in one launch, one block per (ky, kz) plane of a column kx.
+bool yz_plane_supported(const Dims& d);
+hipError_t launch_yz_plane(const Dims& d, float2* S, const float2* tw_y, const float2* tw_z, const float* ws,
+                           const float2* cs, const float* w0p, const float* wnyq, const float2* c0p,
+                           const float2* cnyq, hipStream_t st);
 hipError_t launch_dc_nyquist(const Dims& d, float2* S, const float2* tw_z, const float* w0p,
                              const float* wnyq, const float2* c0p, const float2* cnyq, double* partials,
                              hipStream_t st, int* nblocks_out);

@@ -200,14 +200,16 @@ struct FftPlan {
   static constexpr int T = largest_divisor_le(plan_gcd(L), 16);
 };
 
+// act = false: the thread takes part in the barriers only.
 template <int L, int T, int R, bool INV>
 __device__ __forceinline__ void fft_stage(float* __restrict__ re, float* __restrict__ im, int ps, int q, int Ns,
-                                          const float2* __restrict__ tw) {
+                                          const float2* __restrict__ tw, bool act = true) {
   constexpr int NB = L / (R * T);
   constexpr int STRIDE = L / R;
   float2 a[NB][R];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
+    if (!act) break;
     const int j = q + T * b;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -218,6 +220,7 @@ __device__ __forceinline__ void fft_stage(float* __restrict__ re, float* __restr
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
+    if (!act) break;
     const int j = q + T * b;
     const int k = j % Ns;
     if (Ns > 1) {
@@ -242,19 +245,21 @@ __device__ __forceinline__ void fft_stage(float* __restrict__ re, float* __restr
 }
 
 template <int L, int TT, int S, bool INV>
-__device__ __forceinline__ void lds_stages(float* re, float* im, int ps, int q, int Ns, const float2* tw) {
+__device__ __forceinline__ void lds_stages(float* re, float* im, int ps, int q, int Ns, const float2* tw,
+                                           bool act = true) {
   constexpr RadixList pl = make_plan(L);
   if constexpr (S < pl.n) {
     constexpr int R = pl.r[S];
-    fft_stage<L, TT, R, INV>(re, im, ps, q, Ns, tw);
-    lds_stages<L, TT, S + 1, INV>(re, im, ps, q, Ns * R, tw);
+    fft_stage<L, TT, R, INV>(re, im, ps, q, Ns, tw, act);
+    lds_stages<L, TT, S + 1, INV>(re, im, ps, q, Ns * R, tw, act);
   }
 }
 
 template <int L, bool INV, int TT = FftPlan<L>::T>
-__device__ __forceinline__ void fft_lds(float* re, float* im, int ps, int q, const float2* __restrict__ tw) {
+__device__ __forceinline__ void fft_lds(float* re, float* im, int ps, int q, const float2* __restrict__ tw,
+                                        bool act = true) {
   __syncthreads();
-  lds_stages<L, TT, 0, INV>(re, im, ps, q, 1, tw);
+  lds_stages<L, TT, 0, INV>(re, im, ps, q, 1, tw, act);
 }
 
 // Threads per column of the packed kx = 0 / nx/2 plane kernel: only ny/2 + 1 blocks of two
@@ -829,6 +834,114 @@ __global__ void __launch_bounds__(256) k_dc_nyquist(float2* __restrict__ S, int 
   fft_lds<L, true, T>(re, im, 2, q, tw);
   if (c == 0 || ky != kyp)
     for (int p = q; p < L; p += T) S[base + p * pstride] = make_float2(re[p * 2], im[p * 2]);
+}
+
+// Layout of the folded weight and data term (read only by the fused z pass): groups of
+// WC_G = min(16, P) consecutive kx, each group contiguous along kz, i.e.
+// [ky][kx / WC_G][kz][kx % WC_G], so that a 16-column tile reads them as one contiguous
+// run along z instead of 64- and 128-byte pieces a plane apart.
+__host__ __device__ __forceinline__ int wc_group(int P) { return P < 16 ? P : 16; }
+__device__ __forceinline__ long long wc_index(const Dims& d, int kz, int ky, int kx) {
+  const int G = wc_group(d.P);
+  return (((long long)ky * (d.P / G) + kx / G) * d.nz + kz) * G + kx % G;
+}
+
+// ---------------------------------------------------------------- small maps: y, z passes in one launch
+// Where a (ky, kz) plane of the packed spectrum fits in LDS, one block per column kx does
+// for its plane what k_fft_cols<ny, 0>, k_fft_zw<nz, 2>, k_dc_nyquist and k_fft_cols<ny, 1>
+// do between them: the y then z forward transforms, the weight step (G = w~ Y - c; at kx = 0
+// the packed kx = 0 / nx/2 plane, split and rejoined as in k_dc_nyquist, its partners
+// (-ky, -kz) being in the same plane), and the z then y inverse transforms.  One launch
+// instead of four for maps whose iteration time is launch latency.  Plane in LDS [kz][ky].
+
+// The ntr transforms of L points at base t * tstride and point stride ps, G = 256 / T at a
+// time; every thread takes part in every barrier.
+template <int L, bool INV>
+__device__ __forceinline__ void plane_pass(float* re, float* im, int ntr, int tstride, int ps,
+                                           const float2* __restrict__ tw) {
+  constexpr int T = FftPlan<L>::T;
+  constexpr int G = 256 / T;
+  const int tid = threadIdx.x;
+  for (int c0 = 0; c0 < ntr; c0 += G) {
+    const int t = c0 + tid / T;
+    const bool act = t < ntr && tid < G * T;
+    const int off = act ? t * tstride : 0;
+    fft_lds<L, INV, T>(re + off, im + off, ps, tid % T, tw, act);
+  }
+}
+
+template <int NY, int NZ>
+__global__ void __launch_bounds__(256) k_yz_plane(Dims d, float2* __restrict__ S, const float2* __restrict__ twy,
+                                                  const float2* __restrict__ twz, const float* __restrict__ ws,
+                                                  const float2* __restrict__ cs, const float* __restrict__ w0p,
+                                                  const float* __restrict__ wnyq, const float2* __restrict__ c0p,
+                                                  const float2* __restrict__ cnyq) {
+  constexpr int NP = NY * NZ;
+  __shared__ float s_re[NP];
+  __shared__ float s_im[NP];
+  __shared__ float2 s_twy[NY];
+  __shared__ float2 s_twz[NZ];
+  const int tid = threadIdx.x;
+  const int kx = blockIdx.x;
+  const int P = d.P;
+  float2* __restrict__ Sc = S + kx;
+  for (int i = tid; i < NY; i += 256) s_twy[i] = twy[i];
+  for (int i = tid; i < NZ; i += 256) s_twz[i] = twz[i];
+  for (int e = tid; e < NP; e += 256) {
+    const float2 v = Sc[(long long)e * P];  // (kz NY + ky) P + kx
+    s_re[e] = v.x;
+    s_im[e] = v.y;
+  }
+  plane_pass<NY, false>(s_re, s_im, NZ, NY, 1, s_twy);
+  plane_pass<NZ, false>(s_re, s_im, NY, 1, NY, s_twz);
+  __syncthreads();
+  if (kx > 0) {
+    for (int e = tid; e < NP; e += 256) {
+      const int kz = e / NY, ky = e % NY;
+      const long long o = wc_index(d, kz, ky, kx);
+      const float wv = ws[o];
+      const float2 cv = cs[o];
+      const float yr = s_re[e], yi = s_im[e];
+      s_re[e] = wv * yr - cv.x;
+      s_im[e] = wv * yi - cv.y;
+    }
+  } else {
+    constexpr int EP = (NP + 255) / 256;
+    float2 nv[EP];
+#pragma unroll
+    for (int i = 0; i < EP; ++i) {
+      const int e = tid + 256 * i;
+      if (e < NP) {
+        const int kz = e / NY, ky = e % NY;
+        const int ep = ((NZ - kz) % NZ) * NY + (NY - ky) % NY;
+        const float2 z1 = make_float2(s_re[e], s_im[e]);
+        const float2 z2 = make_float2(s_re[ep], s_im[ep]);
+        const float2 A = make_float2(0.5f * (z1.x + z2.x), 0.5f * (z1.y - z2.y));
+        const float2 dd = make_float2(0.5f * (z1.x - z2.x), 0.5f * (z1.y + z2.y));
+        const float2 B = make_float2(dd.y, -dd.x);
+        const long long offn = (long long)ky * NZ + kz;
+        const float w0 = w0p[offn], wn = wnyq[offn];
+        const float2 c0 = c0p ? c0p[offn] : make_float2(0.f, 0.f);
+        const float2 cn = cnyq ? cnyq[offn] : make_float2(0.f, 0.f);
+        const float2 g0 = make_float2(w0 * A.x - c0.x, w0 * A.y - c0.y);
+        const float2 gn = make_float2(wn * B.x - cn.x, wn * B.y - cn.y);
+        nv[i] = make_float2(g0.x - gn.y, g0.y + gn.x);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < EP; ++i) {
+      const int e = tid + 256 * i;
+      if (e < NP) {
+        s_re[e] = nv[i].x;
+        s_im[e] = nv[i].y;
+      }
+    }
+  }
+  plane_pass<NZ, true>(s_re, s_im, NY, 1, NY, s_twz);
+  plane_pass<NY, true>(s_re, s_im, NZ, NY, 1, s_twy);
+  __syncthreads();
+  for (int e = tid; e < NP; e += 256) Sc[(long long)e * P] = make_float2(s_re[e], s_im[e]);
 }
 
 // ---------------------------------------------------------------- x-axis real FFTs
@@ -1984,15 +2097,6 @@ __device__ __forceinline__ int neg_mod(int k, int n) { return k == 0 ? 0 : n - k
 // Hermitian part of w (A x - b)):  w~ = (w_k + w_{-k})/2,  c = (w_k b_k + w_{-k} conj b_{-k})/2,
 // stored scaled for unnormalised transforms: ws = w~ / nvox, cs = c / sqrt(nvox).
 // Partial: max w~.
-// Layout of the folded weight and data term (read only by the fused z pass): groups of
-// WC_G = min(16, P) consecutive kx, each group contiguous along kz, i.e.
-// [ky][kx / WC_G][kz][kx % WC_G], so that a 16-column tile reads them as one contiguous
-// run along z instead of 64- and 128-byte pieces a plane apart.
-__host__ __device__ __forceinline__ int wc_group(int P) { return P < 16 ? P : 16; }
-__device__ __forceinline__ long long wc_index(const Dims& d, int kz, int ky, int kx) {
-  const int G = wc_group(d.P);
-  return (((long long)ky * (d.P / G) + kx / G) * d.nz + kz) * G + kx % G;
-}
 
 __global__ void __launch_bounds__(256) k_fold(Dims d, const float* __restrict__ w, const float2* __restrict__ b,
                                               float* __restrict__ ws, float* __restrict__ w0p,
@@ -2612,6 +2716,27 @@ hipError_t launch_fft_cols(const Dims& d, float2* S, int axis, int mode, const f
   }
 #undef SPG_ZW
 #undef SPG_ZWN
+  return hipErrorInvalidValue;
+}
+
+bool yz_plane_supported(const Dims& d) {
+  auto ok = [](int n) { return n == 8 || n == 16 || n == 32 || n == 64; };
+  return ok(d.ny) && ok(d.nz);
+}
+
+hipError_t launch_yz_plane(const Dims& d, float2* S, const float2* tw_y, const float2* tw_z, const float* ws,
+                           const float2* cs, const float* w0p, const float* wnyq, const float2* c0p,
+                           const float2* cnyq, hipStream_t st) {
+  if (!yz_plane_supported(d)) return hipErrorInvalidValue;
+#define SPG_YZ(NY_, NZ_)                                                                                      \
+  if (d.ny == NY_ && d.nz == NZ_) {                                                                         \
+    k_yz_plane<NY_, NZ_><<<d.P, 256, 0, st>>>(d, S, tw_y, tw_z, ws, cs, w0p, wnyq, c0p, cnyq);                \
+    return hipGetLastError();                                                                               \
+  }
+#define SPG_YZ4(NY_) SPG_YZ(NY_, 8) SPG_YZ(NY_, 16) SPG_YZ(NY_, 32) SPG_YZ(NY_, 64)
+  SPG_YZ4(8) SPG_YZ4(16) SPG_YZ4(32) SPG_YZ4(64)
+#undef SPG_YZ4
+#undef SPG_YZ
   return hipErrorInvalidValue;
 }
 
