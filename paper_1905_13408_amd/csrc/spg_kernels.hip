@@ -309,9 +309,20 @@ __device__ __forceinline__ int swz(int e) {
   }
 }
 
+// Orders the LDS accesses of one wavefront across this point.  A wavefront executes its LDS
+// instructions in order, so data exchanged among its own lanes needs no s_barrier; this only
+// keeps the compiler from moving accesses across.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // act = false: the thread takes part in the barriers only (blocks whose threads do not all
-// hold a transform).  SWZ: LDS placement by swz (row transforms, ps = 1).
-template <int L, int TT, int S, bool INV, bool SWZ = false>
+// hold a transform).  SWZ: LDS placement by swz (row transforms, ps = 1).  WS: every
+// transform lies within one wavefront, so the stage orders its LDS accesses with wave_sync
+// instead of block barriers.
+template <int L, int TT, int S, bool INV, bool SWZ = false, bool WS = false>
 __device__ __forceinline__ void reg_stage(float2 (&a)[reg_e(L, TT)], float* __restrict__ re,
                                           float* __restrict__ im, int ps, int q, const float2* __restrict__ twl,
                                           bool act = true) {
@@ -340,7 +351,10 @@ __device__ __forceinline__ void reg_stage(float2 (&a)[reg_e(L, TT)], float* __re
       }
     }
   }
-  if constexpr (!first && !last) __syncthreads();
+  if constexpr (!first && !last) {
+    if constexpr (WS) wave_sync();
+    else __syncthreads();
+  }
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     if (!act) break;
@@ -372,7 +386,10 @@ __device__ __forceinline__ void reg_stage(float2 (&a)[reg_e(L, TT)], float* __re
       }
     }
   }
-  if constexpr (!last) __syncthreads();
+  if constexpr (!last) {
+    if constexpr (WS) wave_sync();
+    else __syncthreads();
+  }
 }
 
 template <int L, int TT, int S, bool INV, int SEND = RegPlan<L, TT>::ns, bool SWZ = false>
@@ -390,15 +407,6 @@ template <int L, bool INV, int TT = FftPlan<L>::T, bool SWZ = false>
 __device__ __forceinline__ void fft_reg(float2 (&a)[reg_e(L, TT)], float* re, float* im, int ps, int q,
                                         const float2* twl, bool act = true) {
   reg_stages<L, TT, 0, INV, RegPlan<L, TT>::ns, SWZ>(a, re, im, ps, q, twl, act);
-}
-
-// Orders the LDS accesses of one wavefront across this point.  A wavefront executes its LDS
-// instructions in order, so data exchanged among its own lanes needs no s_barrier; this only
-// keeps the compiler from moving accesses across.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // fft_reg<256, false, 32, true> (the 512-point real rows of a 512-wide map) with its LDS
@@ -1459,8 +1467,8 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
                                                      const float2* __restrict__ twn, int nty) {
   constexpr bool COMP = ST == ST_COMP;
   constexpr bool BF = ST == ST_BF16;
-  // 512-wide maps: the row transforms are pipelined with the plane steps (see below)
-  constexpr bool PIPE = NX == 512;
+  // 256- and 512-wide maps: the row transforms are pipelined with the plane steps (see below)
+  constexpr bool PIPE = NX == 512 || NX == 256;
   constexpr int TY = PF_TY, KB = PIPE ? PP_KB : PF_KB;
   constexpr int M = NX / 2;
   constexpr int FT = PfT<M>::T, FE = PfT<M>::E;
@@ -1469,7 +1477,8 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
   using VT = typename std::conditional<BF, uint16_t, float>::type;  // penalty-weight word
   constexpr int NO = TY / 2;  // own rows per thread
   static_assert(TY % 2 == 0 && 2 * NR * FT == (PIPE ? NX : 2 * NX), "one transform row share per thread");
-  static_assert(!PIPE || (M == 256 && FT == 32 && FE == 8), "the pipelined variant runs 512-wide maps");
+  static_assert(!PIPE || (FE == 8 && 64 % FT == 0 && RegPlan<M, FT>::ns == 3),
+                "pipelined rows: 8 points per lane, a row within one wavefront, three stages");
   __shared__ float sY[3][TY + 2][NX];
   __shared__ float sSC[2][TY + 1][NX];
   __shared__ float sG[NG][KB][TY][NX];  // gradient rows of a batch, then its y_{k+1} rows
@@ -1484,9 +1493,9 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
   const int tid = threadIdx.x;
   int x = tid % NX, r = tid / NX;
   int xm = (x + NX - 1) % NX, xp = (x + 1) % NX;
-  // 512-wide maps: neighbouring tiles on one XCD, so that the halo rows a tile reads are
-  // often still in that XCD's L2 from its neighbours' own rows (measured 3% faster; no gain
-  // with the batched transforms, which leave the memory pipe idle for longer)
+  // Pipelined kernel: neighbouring tiles on one XCD, so that the halo rows a tile reads are
+  // often still in that XCD's L2 from its neighbours' own rows (measured 3% faster at
+  // nx = 512; no gain with the batched transforms, which leave the memory pipe idle longer)
   const int bid = PIPE ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
   const int by = bid % nty;
   const int bz = bid / nty;
@@ -1844,6 +1853,25 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
     const bool pfwd = fr < NR;           // wave-uniform
     const int prow = pfwd ? fr : fr - NR;
     const int mb = M - fq - FT * (FE - 1);  // mirror base, as in transform_phase
+    // the three stages of a row transform: at M = 256 the Row256 stages, else the generic
+    // register stages with wave-level ordering (same operations as fft_reg)
+    auto stage0 = [&](float2(&v)[FE], float* fre, float* fim, bool act) {
+      if constexpr (M == 256) Row256::s0(v, fre, fim, fq, act);
+      else reg_stage<M, FT, 0, false, true, true>(v, fre, fim, 1, fq, s_tw, act);
+    };
+    auto stage1 = [&](float2(&v)[FE], float* fre, float* fim, bool act) {
+      if constexpr (M == 256) {
+        Row256::s1r(v, fre, fim, fq, act);
+        wave_sync();
+        Row256::s1w(v, fre, fim, fq, s_tw, act);
+      } else {
+        reg_stage<M, FT, 1, false, true, true>(v, fre, fim, 1, fq, s_tw, act);
+      }
+    };
+    auto stage2 = [&](float2(&v)[FE], float* fre, float* fim, bool act) {
+      if constexpr (M == 256) Row256::s2(v, fre, fim, fq, s_tw, act);
+      else reg_stage<M, FT, 2, false, true, true>(v, fre, fim, 1, fq, s_tw, act);
+    };
     // chunk 1: forward rows of the batch at zf (planes < zf_end) out of slot gf; inverse
     // rows: the spectrum in sa, then Z (as k_c2r_x, conjugated); radix-8 stage 0 of both
     auto chunk1 = [&](int zf, int zf_end, int gf, int zi) {
@@ -1884,7 +1912,7 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
         }
         wave_sync();
       }
-      Row256::s0(v, fre, fim, fq, act);
+      stage0(v, fre, fim, act);
     };
     auto pact = [&](int zf, int zf_end, int zi) {
       return pfwd ? zf + prow / TY < zf_end : zi + prow / TY < z1;
@@ -1895,9 +1923,7 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
       const bool act = pact(zf, zf_end, zi);
       float2 v[FE];
       float* fre = &sFx[fr * 2 * M];
-      Row256::s1r(v, fre, fre + M, fq, act);
-      wave_sync();
-      Row256::s1w(v, fre, fre + M, fq, s_tw, act);
+      stage1(v, fre, fre + M, act);
     };
     // chunk 3: radix-4 stage 2; inverse rows: real samples into slot gi; forward rows: Z
     // into the row for the mirror reads of chunk 4
@@ -1907,7 +1933,7 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
       float* fre = &sFx[fr * 2 * M];
       float* fim = fre + M;
       float2 v[FE];
-      Row256::s2(v, fre, fim, fq, s_tw, act);
+      stage2(v, fre, fim, act);
       if (!act) return;
       if (pfwd) {
         wave_sync();
