@@ -325,7 +325,10 @@ spg_status spg_fsc(int32_t nx, int32_t ny, int32_t nz, const float* d_map1, cons
 spg_status spg_fsc_noalloc(int32_t nx, int32_t ny, int32_t nz, const float* d_map1, const float* d_map2,
                            int32_t nshells, void* hip_stream, double* h_fsc);
 
-/* Kernel classes for spg_profile_begin. */
+/* Kernel classes for spg_profile_begin.  On maps whose spectrum outgrows the 256 MiB
+ * last-level cache the y forward, z and y inverse passes are launched as four column
+ * ranges each (four launches per class and iteration); on small maps (ny, nz <= 64) one
+ * launch does all three passes and the packed plane and is counted as the z class. */
 typedef enum {
   SPG_KERNEL_FFT_Y_FWD = 0, /* y-axis forward column FFT                               */
   SPG_KERNEL_FFT_Z_WEIGHT,  /* z-axis forward FFT, Fourier weight multiply, inverse FFT  */
@@ -341,7 +344,8 @@ typedef enum {
 
 /* Profiling: time launches with HIP events recorded on the problem's stream around each
  * of them -- every launch of one kernel class, or of every class with SPG_KERNEL_ALL --
- * for at most `capacity` launches per class.  spg_profile_end synchronises and writes
+ * for at most `capacity` launches per class (launches past it are not timed and not
+ * counted).  spg_profile_end synchronises and writes
  * per-class totals to total_ms[SPG_KERNEL_COUNT] (device ms) and
  * launches[SPG_KERNEL_COUNT]; either may be NULL. */
 spg_status spg_profile_begin(spg_problem* P, int32_t kernel_class, int32_t capacity);
