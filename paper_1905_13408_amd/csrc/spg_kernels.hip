@@ -1709,7 +1709,7 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
   RawX rown[NO], rhalo;
   float rv[NO + 1];
   double own_y[NO], own_xk[NO], nxt_y[NO], nxt_xk[NO];
-  float u_cur[NO], xq_cur[NO];
+  float u_cur[NO], xq_cur[NO], u_nxt[NO], xq_nxt[NO];
   auto step_a = [&](int z) {
     // The lane indices pass through empty asm statements so that the LDS and global
     // addresses derived from them are formed inside the loop where they are used, not
@@ -1720,6 +1720,7 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
     asm volatile("" : "+v"(fr), "+v"(fq));
     store_plane(z + 1, rown, rhalo, nxt_y, nxt_xk);
     if (z + 1 < z1) fetch_x(z + 2, rown, rhalo);
+    if (z + 1 < z1) fetch_out(z + 1, u_nxt, xq_nxt);
   };
   // second half (after a barrier): sc(z+1) into its ring slot (read by the next step) and,
   // for this thread's own voxels, straight into the outputs of plane z, whose y_{k+1} rows
@@ -1791,11 +1792,12 @@ __global__ void __launch_bounds__(2 * NX) k_prox_fft(ProxArgs a, float2* __restr
         G[ly][x] = ynext;
       }
     }
-    if (z + 1 < z1) fetch_out(z + 1, u_cur, xq_cur);
 #pragma unroll
     for (int h = 0; h < NO; ++h) {
       own_y[h] = nxt_y[h];
       own_xk[h] = nxt_xk[h];
+      u_cur[h] = u_nxt[h];
+      xq_cur[h] = xq_nxt[h];
     }
   };
 
