@@ -699,8 +699,7 @@ __global__ void __launch_bounds__(16 * ColT<L>::T) k_fft_zw(float2* __restrict__
     float2 nxt[E];
     float wv[E];
     float2 cv[E];
-    reg_stages<L, T, 0, false, 1>(a, re, im, NT, ql, s_tw);
-    // the folded weight and data term load during the remaining forward stages
+    // the folded weight and data term load during the forward stages
     const long long wb = wc_base(t);
     const unsigned ow = wc_off(t);
     const float* __restrict__ wsb = ws + wb;
@@ -714,6 +713,7 @@ __global__ void __launch_bounds__(16 * ColT<L>::T) k_fft_zw(float2* __restrict__
 #pragma unroll
       for (int i = 0; i < E; ++i) cv[i] = make_float2(0.f, 0.f);
     }
+    reg_stages<L, T, 0, false, 1>(a, re, im, NT, ql, s_tw);
     reg_stages<L, T, 1, false>(a, re, im, NT, ql, s_tw);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
