@@ -293,8 +293,11 @@ spg_status spg_vjp(spg_problem* P, void* d_vjp_ws, size_t bytes, const float* d_
  * b = num / N (0 where N = 0; nz*ny*nx complex, interleaved), ready for spg_set_data.
  * d_images: n_img*m*m complex; d_rot: n_img row-major 3x3 double matrices; d_ctf: n_img*m*m
  * float or NULL (1); d_weight: n_img posterior weights or NULL (1).  Device pointers; the
- * workspace (spg_backproject_workspace_size bytes, 8-byte aligned) holds fp64 accumulators;
- * asynchronous on hip_stream.  fp64 atomics: sums can differ between runs in the last bits. */
+ * workspace (spg_backproject_workspace_size bytes, 8-byte aligned) holds the accumulators;
+ * asynchronous on hip_stream.  The sums are int64 fixed point with a power-of-two scale per
+ * component (chosen from the largest term and the pixel count so that no sum can overflow;
+ * terms are rounded at 2^-62 of that bound), so results are bitwise reproducible and do not
+ * depend on the order of the images. */
 spg_status spg_backproject_workspace_size(int32_t nx, int32_t ny, int32_t nz, size_t* bytes);
 spg_status spg_backproject(int32_t nx, int32_t ny, int32_t nz, int32_t n_img, int32_t m, const float* d_images,
                            const double* d_rot, const float* d_ctf, const float* d_weight, double h,

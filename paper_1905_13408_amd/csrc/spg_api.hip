@@ -1518,7 +1518,7 @@ extern "C" {
 
 spg_status spg_backproject_workspace_size(int32_t nx, int32_t ny, int32_t nz, size_t* bytes) {
   if (!bytes || nx < 1 || ny < 1 || nz < 1 || nx > 1024 || ny > 1024 || nz > 1024) return SPG_E_INVAL;
-  *bytes = align_up(3 * (size_t)nx * ny * nz * sizeof(double));
+  *bytes = align_up((3 * (size_t)nx * ny * nz + 3) * sizeof(uint64_t));
   return SPG_OK;
 }
 
@@ -1533,7 +1533,7 @@ spg_status spg_backproject(int32_t nx, int32_t ny, int32_t nz, int32_t n_img, in
   if (bytes < need) return SPG_E_NOMEM;
   Dims d{nx, ny, nz, nx / 2, (long long)nx * ny * nz};
   if (launch_backproject(d, n_img, m, reinterpret_cast<const float2*>(d_images), d_rot, d_ctf, d_weight, h,
-                         reinterpret_cast<double*>(d_workspace), d_w_out, reinterpret_cast<float2*>(d_b_out),
+                         d_workspace, d_w_out, reinterpret_cast<float2*>(d_b_out),
                          reinterpret_cast<hipStream_t>(hip_stream)) != hipSuccess)
     return SPG_E_DEVICE;
   return SPG_OK;

@@ -125,7 +125,7 @@ hipError_t launch_adj_tv(const Dims& d, const float* xk, const float* xkm, float
                          double* partials, int nblocks, hipStream_t st);
 hipError_t launch_expand_bbar(const Dims& d, const float2* S, const float* w, float2* out, hipStream_t st);
 hipError_t launch_backproject(const Dims& d, int n_img, int m, const float2* images, const double* rots,
-                              const float* ctf, const float* weights, double h, double* acc, float* w, float2* b,
+                              const float* ctf, const float* weights, double h, void* ws, float* w, float2* b,
                               hipStream_t st);
 hipError_t launch_fsc_shells(const Dims& d, const float2* S1, const float2* S2, int nshells, double* partials,
                              int nblocks, double* out, hipStream_t st);

@@ -2518,17 +2518,66 @@ __global__ void __launch_bounds__(256) k_expand_bbar(Dims d, const float2* __res
 }
 
 // ---------------------------------------------------------------- backprojection (eq 24-29)
+// The three sums (Re num, Im num, N) are accumulated as int64 fixed-point numbers, whose
+// atomic additions give the same bits in any order: every term is rounded to a multiple of
+// 2^-s_c, with s_c chosen so that B_c 2^s_c < 2^62 for a bound B_c on the component's sum
+// of magnitudes at any grid point.  B_c is 27 times the number of pixels times the largest
+// term magnitude (|p ctf Re X|, |p ctf Im X| or p ctf^2; K <= 1), so no partial sum leaves
+// the int64 range.  The maxima are exact whatever
+// the order of their atomics.
+
+// The largest |p ctf Re X|, |p ctf Im X| and p ctf^2 over all pixels, kept as the bit
+// patterns of non-negative doubles (which order like their values) in mx[0..3).
+__global__ void __launch_bounds__(256) k_bp_max(int n_img, int m, const float2* __restrict__ images,
+                                                const float* __restrict__ ctf, const float* __restrict__ weights,
+                                                unsigned long long* __restrict__ mx) {
+  __shared__ double s_red[4];
+  const long long npix = (long long)m * m;
+  const long long total = npix * n_img;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total; t += (long long)gridDim.x * blockDim.x) {
+    const float2 X = images[t];
+    const double cf = ctf ? (double)ctf[t] : 1.0;
+    const double p = weights ? (double)weights[t / npix] : 1.0;
+    a0 = fmax(a0, fabs(p * cf * X.x));
+    a1 = fmax(a1, fabs(p * cf * X.y));
+    a2 = fmax(a2, fabs(p * cf * cf));
+  }
+  a0 = block_reduce<RED_OP_MAX>(a0, s_red);
+  a1 = block_reduce<RED_OP_MAX>(a1, s_red);
+  a2 = block_reduce<RED_OP_MAX>(a2, s_red);
+  if (threadIdx.x == 0) {
+    atomicMax(&mx[0], (unsigned long long)__double_as_longlong(a0));
+    atomicMax(&mx[1], (unsigned long long)__double_as_longlong(a1));
+    atomicMax(&mx[2], (unsigned long long)__double_as_longlong(a2));
+  }
+}
+
+// 2^s for the component whose largest term magnitude has the bits `mx`: the power of two
+// that puts the bound just below 2^62.  The bound is 27 terms per pixel at most (on axes
+// shorter than 3 points the 27 neighbours of a coefficient wrap onto fewer grid points).
+__device__ __forceinline__ double bp_scale(unsigned long long mx, long long total) {
+  const double bound = __longlong_as_double((long long)mx) * (double)total * 27.0;
+  if (!(bound > 0.0) || !(bound < 1e300)) return 1.0;
+  int e = 0;
+  frexp(bound, &e);  // bound < 2^e
+  return ldexp(1.0, 62 - e);
+}
+
 // One thread per (image, pixel): the coefficient X at signed frequency (u, v) lands at
 // c = R (u, v, 0)^T (eq 24) and is spread over the 3^3 grid points round(c) + delta with
-// K = exp(-|c - n|^2 / h), accumulating num += p K ctf X and N += p K ctf^2 (eq 28) in fp64
-// atomics.  The coordinate products are rounded separately (no fused multiply-add) so that
-// the rounding of c, which decides the neighbourhood, is the reference's.
+// K = exp(-|c - n|^2 / h), accumulating num += p K ctf X and N += p K ctf^2 (eq 28) as
+// fixed-point terms.  The coordinate products are rounded separately (no fused
+// multiply-add) so that the rounding of c, which decides the neighbourhood, is the
+// reference's.
 __global__ void __launch_bounds__(256) k_backproject(Dims d, int n_img, int m, const float2* __restrict__ images,
                                                      const double* __restrict__ rots, const float* __restrict__ ctf,
                                                      const float* __restrict__ weights, double h,
-                                                     double* __restrict__ acc) {
+                                                     unsigned long long* __restrict__ acc,
+                                                     const unsigned long long* __restrict__ mx) {
   const long long npix = (long long)m * m;
   const long long total = npix * n_img;
+  const double s0 = bp_scale(mx[0], total), s1 = bp_scale(mx[1], total), s2 = bp_scale(mx[2], total);
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total; t += (long long)gridDim.x * blockDim.x) {
     const int i = (int)(t / npix);
     const int pix = (int)(t - (long long)i * npix);
@@ -2546,7 +2595,7 @@ __global__ void __launch_bounds__(256) k_backproject(Dims d, int n_img, int m, c
     const float2 X = images[t];
     const double cf = ctf ? (double)ctf[t] : 1.0;
     const double p = weights ? (double)weights[i] : 1.0;
-    const double wr = p * cf * X.x, wi = p * cf * X.y, ww = p * cf * cf;
+    const double wr = p * cf * X.x * s0, wi = p * cf * X.y * s1, ww = p * cf * cf * s2;
     for (int dz = -1; dz <= 1; ++dz)
       for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
@@ -2556,20 +2605,25 @@ __global__ void __launch_bounds__(256) k_backproject(Dims d, int n_img, int m, c
           const long long ix = ((gx % d.nx) + d.nx) % d.nx, iy = ((gy % d.ny) + d.ny) % d.ny,
                           iz = ((gz % d.nz) + d.nz) % d.nz;
           const long long idx = (iz * d.ny + iy) * d.nx + ix;
-          atomicAdd(&acc[idx], K * wr);
-          atomicAdd(&acc[d.nvox + idx], K * wi);
-          atomicAdd(&acc[2 * d.nvox + idx], K * ww);
+          atomicAdd(&acc[idx], (unsigned long long)__double2ll_rn(K * wr));
+          atomicAdd(&acc[d.nvox + idx], (unsigned long long)__double2ll_rn(K * wi));
+          atomicAdd(&acc[2 * d.nvox + idx], (unsigned long long)__double2ll_rn(K * ww));
         }
   }
 }
 
-// w = N, b = num / N (0 where N = 0).
-__global__ void k_backproject_final(long long n, const double* __restrict__ acc, float* __restrict__ w,
+// w = N, b = num / N (0 where N = 0), the fixed-point sums scaled back by their exact
+// powers of two.
+__global__ void k_backproject_final(long long n, long long total, const unsigned long long* __restrict__ acc,
+                                    const unsigned long long* __restrict__ mx, float* __restrict__ w,
                                     float2* __restrict__ b) {
+  const double r0 = 1.0 / bp_scale(mx[0], total), r1 = 1.0 / bp_scale(mx[1], total),
+               r2 = 1.0 / bp_scale(mx[2], total);
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    const double den = acc[2 * n + i];
+    const double den = (double)(long long)acc[2 * n + i] * r2;
+    const double nr = (double)(long long)acc[i] * r0, ni = (double)(long long)acc[n + i] * r1;
     w[i] = (float)den;
-    b[i] = den > 0 ? make_float2((float)(acc[i] / den), (float)(acc[n + i] / den)) : make_float2(0.f, 0.f);
+    b[i] = den > 0 ? make_float2((float)(nr / den), (float)(ni / den)) : make_float2(0.f, 0.f);
   }
 }
 
@@ -3001,17 +3055,22 @@ hipError_t launch_expand_bbar(const Dims& d, const float2* S, const float* w, fl
 }
 
 hipError_t launch_backproject(const Dims& d, int n_img, int m, const float2* images, const double* rots,
-                              const float* ctf, const float* weights, double h, double* acc, float* w, float2* b,
+                              const float* ctf, const float* weights, double h, void* ws, float* w, float2* b,
                               hipStream_t st) {
-  k_fill_f64<<<ew_grid(3 * d.nvox), 256, 0, st>>>(acc, 3 * d.nvox);
+  // workspace: 3 nvox fixed-point sums, then the 3 term maxima (all zero bits to start)
+  unsigned long long* acc = static_cast<unsigned long long*>(ws);
+  unsigned long long* mx = acc + 3 * d.nvox;
+  k_fill_f64<<<ew_grid(3 * d.nvox + 3), 256, 0, st>>>(static_cast<double*>(ws), 3 * d.nvox + 3);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long long total = (long long)n_img * m * m;
   long long g = (total + 255) / 256;
   if (g > 65536) g = 65536;
-  k_backproject<<<(unsigned)g, 256, 0, st>>>(d, n_img, m, images, rots, ctf, weights, h, acc);
+  k_bp_max<<<(unsigned)(g < 1024 ? g : 1024), 256, 0, st>>>(n_img, m, images, ctf, weights, mx);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  k_backproject_final<<<ew_grid(d.nvox), 256, 0, st>>>(d.nvox, acc, w, b);
+  k_backproject<<<(unsigned)g, 256, 0, st>>>(d, n_img, m, images, rots, ctf, weights, h, acc, mx);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_backproject_final<<<ew_grid(d.nvox), 256, 0, st>>>(d.nvox, total, acc, mx, w, b);
   return hipGetLastError();
 }
 

@@ -683,6 +683,12 @@ def test_backprojection_matches_oracle(shape, m, n_img):
     eb = rel_l2(b.cpu().numpy().view(np.float32).astype(np.float64), ob.astype(np.complex128).view(np.float64))
     print(f"backprojection rel L2: w {ew:.3e}, b {eb:.3e}", flush=True)
     assert ew < 1e-6 and eb < 1e-5
+    # the fixed-point sums do not depend on the order of the images: a permuted stack gives
+    # the same bits
+    perm = rng.permutation(n_img)
+    w2, b2 = spg.backproject(shape, torch.from_numpy(imgs[perm]).cuda(), torch.from_numpy(rots[perm]).cuda(),
+                             torch.from_numpy(ctf[perm]).cuda(), torch.from_numpy(wts[perm]).cuda(), h=2.0)
+    assert torch.equal(w2, w) and torch.equal(b2, b)
     # the products feed the solver directly
     s = spg.SPGSolver(shape, 0.01, 0.05, 1e-2)
     s.set_data(w, b)
